@@ -1,0 +1,229 @@
+/*
+ * vsfe.h - C ABI of the MI355X (gfx950) stereo visual-SLAM front-end.
+ *
+ * The library computes, for a batch of images (stereo pairs are images 2i
+ * and 2i+1), the GPU front-end of "High-Speed Stereo Visual SLAM for
+ * Low-Powered Computing Devices" (Kumar, Park, Behera, RA-L 2023):
+ *   pyramid_build        image pyramid at scale 1.2 (Sec. III-2)
+ *   fast_br_detect       FAST with Bounded Rectification (Sec. II-A, Eq. 1-3),
+ *                        corner response (Sec. III-1), fused Feature Culling
+ *                        (Sec. II-C-1)
+ *   pyca_cull_aggregate  Pyramidal Feature Aggregation with sparse NMS
+ *                        (Sec. II-C-2, Fig. "pfa") and the keypoint cap
+ *   orb_describe         smoothing, ORB orientation, rBRIEF (Sec. III-2)
+ *   stereo_match         descriptor-distance stereo matching along
+ *                        rectified rows (Sec. III-3, middle-end)
+ *   cnn_*                learned cell proposer gating the detector
+ *
+ * Conventions (all calls):
+ *   - Return value: VSFE_OK or a negative VSFE_E* code.  On error nothing is
+ *     launched and vsfe_last_error() describes the cause.
+ *   - Hot-path calls are asynchronous on the caller's HIP stream (passed as
+ *     void*, NULL = the default stream).  They never allocate, never
+ *     synchronise and never abort; they launch kernels only, so they can be
+ *     captured into a HIP graph.
+ *   - All buffers are device memory owned by the caller, sized with
+ *     vsfe_batch_info_get().  The library owns only the context (constant
+ *     tables) and the batch object (its device work tables); both are made
+ *     at set-up time.
+ *   - A context and a batch are used from one stream at a time.
+ *   - `status` is a caller-zeroed device int32; kernels OR VSFE_DEV_* bits
+ *     into it for conditions only the device can see.
+ */
+#ifndef VSFE_H
+#define VSFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VSFE_OK            0
+#define VSFE_EINVAL       -1   /* null pointer, bad size or parameter      */
+#define VSFE_ECAPACITY    -2   /* a size limit of the library is exceeded  */
+#define VSFE_EHIP         -3   /* a HIP call failed (see vsfe_last_error)  */
+#define VSFE_EUNSUPPORTED -4   /* no gfx950 device / feature not built     */
+
+#define VSFE_DEV_OVERFLOW  1   /* a device-side count exceeded capacity    */
+
+#define VSFE_MAX_LEVELS   12
+#define VSFE_MAX_IMAGES   4096
+#define VSFE_MAX_DIM      8192
+#define VSFE_KP_FALLBACK  1u   /* kp flags bit: found at the fallback threshold */
+#define VSFE_KEY_FALLBACK (1u << 22)   /* cell-key bit: fallback threshold  */
+
+/*
+ * Front-end parameters.  Defaults (vsfe_params_default) follow the paper:
+ * eps = 20 (Sec. II-A), P_min = 9, P_max = 13 (Eq. 3), 32x32 cells at the
+ * native scale, q = 3 NMS window (Sec. II-C-2), 8 levels at scale 1.2.
+ */
+typedef struct vsfe_params {
+    int32_t eps_hi;      /* FAST threshold, 0..254                              */
+    int32_t eps_lo;      /* per-cell fallback threshold, -1 = none, <= eps_hi    */
+    int32_t p_min;       /* shortest accepted contiguous run, 1..16              */
+    int32_t p_max;       /* longest accepted run (16 = plain FAST), >= p_min     */
+    int32_t border;      /* skipped pixels at each level edge, >= 3 (>= 15 to describe) */
+    int32_t n_levels;    /* pyramid levels, 1..VSFE_MAX_LEVELS                   */
+    int32_t cell0;       /* native-scale cell side, 8..32; level l uses
+                            floor(cell0 * 5^l / 6^l), which must stay >= 1       */
+    int32_t pfa;         /* 1 = pyramidal feature aggregation, 0 = culling only  */
+    int32_t nms_mode;    /* 0 = (k_l, k_r) lexicographic, 1 = both larger         */
+    int32_t nms_radius;  /* NMS half-window at the native scale, 0..3 (q = 2r+1) */
+    int32_t n_max;       /* keypoints kept per image, 1..65535                   */
+    int32_t blur;        /* 1 = 7-tap smoothing before rBRIEF sampling           */
+    int32_t d_max;       /* stereo disparity range at the native scale, >= 0     */
+    int32_t match_th;    /* largest accepted Hamming distance, 0..256            */
+    int32_t row_band;    /* |dy| tolerance in level pixels, 0..3                 */
+} vsfe_params;
+
+/* Keypoints, structure of arrays.  Image i owns slots
+ * [i * n_max, i * n_max + kp_count[i]) in canonical order (level, cell row,
+ * cell column).  x, y are level coordinates, x0, y0 their projection to
+ * the native scale; kl / kr are the aggregated level count / response sum
+ * of the keypoint's native-scale position; bin is the orientation in 12-
+ * degree steps (written by orb_describe). */
+typedef struct vsfe_kp_soa {
+    uint16_t *x, *y;
+    uint8_t  *level, *flags;
+    uint16_t *score, *x0, *y0;
+    uint8_t  *kl;
+    uint32_t *kr;
+    uint8_t  *bin;
+} vsfe_kp_soa;
+
+typedef struct vsfe_batch_info {
+    int64_t input_bytes;      /* smallest input buffer covering every image    */
+    int64_t pyr_bytes;        /* pyramid buffer (levels 1..n_levels-1)         */
+    int64_t crf_elems;        /* uint16 elements of the optional response dump */
+    int64_t n_cells;          /* cell_keys elements (all images, all levels)   */
+    int64_t n_cells0;         /* level-0 cells (cell_mask / cell_logits size)  */
+    int64_t kp_capacity;      /* keypoint slots = n_images * n_max             */
+    int64_t workspace_bytes;  /* pyca_cull_aggregate workspace                 */
+    int64_t match_capacity;   /* stereo outputs = n_pairs * n_max              */
+    int32_t n_images;
+    int32_t n_levels;
+} vsfe_batch_info;
+
+typedef struct vsfe_level_info {
+    int32_t width, height, pitch;   /* level size and row pitch in bytes      */
+    int32_t cell, ncx, ncy;         /* cell side and cell grid                */
+    int64_t offset;                 /* level 0: byte offset in the input
+                                       buffer; others: in the pyramid buffer */
+    int64_t cell_offset;            /* first cell of this level in cell_keys  */
+    int64_t crf_offset;             /* first element in the response dump     */
+    int64_t cell0_offset;           /* first level-0 cell of the image        */
+} vsfe_level_info;
+
+typedef struct vsfe_ctx vsfe_ctx;
+typedef struct vsfe_batch vsfe_batch;
+
+/* ---------------------------------------------------------------- set-up */
+
+/* Fill *p with the paper's defaults (see vsfe_params).  Host only. */
+void vsfe_params_default(vsfe_params *p);
+
+/* Validate parameters without touching the GPU.  Host only. */
+int32_t vsfe_params_check(const vsfe_params *p);
+
+/* Level geometry of a W x H image (Sec. III-2 pyramid, Sec. IV-F cell
+ * shrink): W_l = floor(W / 1.2^l + 1/2), cell_l = floor(cell0 * 5^l / 6^l).
+ * Host only; EINVAL for bad sizes. */
+int32_t vsfe_level_geometry(const vsfe_params *p, int32_t W, int32_t H, int32_t level,
+                            int32_t *Wl, int32_t *Hl, int32_t *cell);
+
+/* Create a context on the current HIP device.  `pattern` is a host array of
+ * 256 x 4 int8 (pu, pv, qu, qv) test-point pairs inside the radius-15 disc;
+ * the library stores the 30 rotated copies.  Synchronous.  Errors: EINVAL
+ * (bad params / pattern outside the disc), EUNSUPPORTED (no gfx950),
+ * EHIP. */
+int32_t vsfe_ctx_create(const vsfe_params *p, const int8_t *pattern, vsfe_ctx **out);
+int32_t vsfe_ctx_destroy(vsfe_ctx *ctx);
+
+/* Describe a batch of n images.  widths/heights/pitches/offsets are host
+ * arrays of n entries; image i occupies bytes offsets[i] .. offsets[i] +
+ * pitches[i] * heights[i] of the caller's input buffer.  Builds and uploads
+ * the device work tables (synchronous, set-up time).  Errors: EINVAL
+ * (sizes, a level with no cell, pitch < width), ECAPACITY (n > VSFE_MAX_IMAGES). */
+int32_t vsfe_batch_create(const vsfe_ctx *ctx, int32_t n, const int32_t *widths,
+                          const int32_t *heights, const int32_t *pitches,
+                          const int64_t *offsets, vsfe_batch **out);
+int32_t vsfe_batch_destroy(vsfe_batch *b);
+
+/* Buffer sizes of a batch without creating it (host only, same arguments
+ * and errors as vsfe_batch_create). */
+int32_t vsfe_batch_plan(const vsfe_params *p, int32_t n, const int32_t *widths,
+                        const int32_t *heights, const int32_t *pitches,
+                        const int64_t *offsets, vsfe_batch_info *out);
+int32_t vsfe_batch_info_get(const vsfe_batch *b, vsfe_batch_info *out);
+int32_t vsfe_batch_level_info(const vsfe_batch *b, int32_t image, int32_t level,
+                              vsfe_level_info *out);
+
+/* Tile shape of fast_br_detect: the target tile extent in pixels (each
+ * level packs as many whole cells as fit, at least one).  Host only; takes
+ * effect for batches created afterwards.  EINVAL unless 8 <= tw <= 128,
+ * 8 <= th <= 64. */
+int32_t vsfe_ctx_set_tile(vsfe_ctx *ctx, int32_t tile_w, int32_t tile_h);
+
+/* Last error message of the calling thread ("" if none). */
+const char *vsfe_last_error(void);
+
+/* --------------------------------------------------------------- hot path */
+
+/* Sec. III-2: levels 1..n-1 of every image, each resampled from the level
+ * above by bilinear interpolation at half-pixel centres with Q8 source
+ * coordinates (floored) and Q16 weights rounded half up.  images: input
+ * buffer (level 0, read), pyr: pyramid buffer (written). */
+int32_t pyramid_build(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
+                      uint8_t *pyr, int32_t *status, void *stream);
+
+/* Sec. II-A Eq. 1-3, Sec. III-1 and Sec. II-C-1: for every pixel inside the
+ * border of every level, FAST labels at eps_hi (and eps_lo), the longest
+ * cyclic bright / dark run N, the Bounded-Rectification test
+ * p_min <= N <= p_max, the response sum |I_c - I_p| over the 16-pixel ring,
+ * and per cell the maximum key (score << 10) | (1023 - offset in cell),
+ * falling back to eps_lo corners (bit VSFE_KEY_FALLBACK) when the cell has
+ * no eps_hi corner.  cell_keys (n_cells, written, 0 = empty).
+ * cell_mask (n_cells0 bytes, nullable): learned gating, a level-l cell runs
+ * only if its native-scale footprint overlaps a non-zero level-0 cell.
+ * crf_debug (crf_elems, nullable): per-pixel eps_hi response, 0 elsewhere. */
+int32_t fast_br_detect(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
+                       const uint8_t *pyr, const uint8_t *cell_mask, uint32_t *cell_keys,
+                       uint16_t *crf_debug, int32_t *status, void *stream);
+
+/* Sec. II-C-2 (PFA): projection of every culled keypoint to the native
+ * scale (x0 = round(x * 1.2^l) in Q16), K_l / K_r per native position,
+ * sparse (2r+1)^2 NMS around keypoints, survivors kept at every level, then
+ * the cap to n_max by (k_l desc, k_r desc, canonical order).  With
+ * params.pfa = 0: culling output only (k_l = 1, k_r = score) and the cap.
+ * Writes kps (kp_capacity slots) and kp_count (n_images).  workspace:
+ * workspace_bytes of device scratch. */
+int32_t pyca_cull_aggregate(const vsfe_ctx *ctx, const vsfe_batch *b,
+                            const uint32_t *cell_keys, void *workspace,
+                            const vsfe_kp_soa *kps, int32_t *kp_count, int32_t *status,
+                            void *stream);
+
+/* Sec. III-2: intensity-centroid orientation over the radius-15 disc of the
+ * unsmoothed level, quantised to 30 bins; 256 binary tests on the
+ * bin-rotated pattern over the smoothed level.  Writes kps.bin and desc
+ * (8 uint32 per keypoint slot; bit t is word t >> 5, bit t & 31).
+ * Requires params.border >= 15 (EINVAL otherwise). */
+int32_t orb_describe(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
+                     const uint8_t *pyr, const vsfe_kp_soa *kps, const int32_t *kp_count,
+                     uint32_t *desc, int32_t *status, void *stream);
+
+/* Sec. III-3: for each left keypoint (image 2i) the right keypoint (image
+ * 2i+1) of the same level with |dy| <= row_band and native-scale disparity
+ * d = x0_l - x0_r in [0, d_max] of least Hamming distance (ties: smaller
+ * |dy|, smaller d, smaller index); accepted if distance <= match_th.
+ * Outputs (match_capacity, slot pair * n_max + i): match_idx (right index
+ * or -1), match_dist (0xFFFF if none), match_disp (-1 if none).  EINVAL if
+ * the batch has an odd image count or a pair of unequal sizes. */
+int32_t stereo_match(const vsfe_ctx *ctx, const vsfe_batch *b, const vsfe_kp_soa *kps,
+                     const int32_t *kp_count, const uint32_t *desc, int32_t *match_idx,
+                     uint16_t *match_dist, int16_t *match_disp, int32_t *status, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

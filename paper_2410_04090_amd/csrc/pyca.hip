@@ -1,0 +1,275 @@
+// Pyramidal Feature Aggregation and the keypoint cap (Sec. II-C-2).
+//
+// The paper projects every culled keypoint to the native scale, writes the
+// responses into a dense zero-initialised M[N_s][H][W], sums it into K_r
+// and K_l, and runs a sparse q x q NMS around keypoints.  A dense M costs
+// more HBM bytes than the pyramid itself, so here the same quantities are
+// gathered sparsely: a native-scale position can only receive, from level
+// m, the keypoint of one of the few level-m cells whose pixels project into
+// the (2r+1)^2 window, so each keypoint reads those cells' keys (L2
+// resident) and accumulates K_l / K_r for every window position.  The sums
+// are integers, so the result equals the dense formulation exactly.
+//
+// Kernel 1 (one thread per cell): rank = (K_l << 16) | K_r of surviving
+//   keypoints, 0 for empty or suppressed cells.
+// Kernel 2 (one block per image): if more than n_max survive, a two-pass
+//   radix select finds the n_max-th largest rank T; cells with rank > T and
+//   the first (in canonical order) cells with rank == T are kept; block
+//   prefix sums compact the survivors into the keypoint arrays in canonical
+//   order (level, cell row, cell column).
+#include "vsfe_internal.h"
+
+namespace vsfe {
+
+__device__ __forceinline__ int project_q16(int x, int S, int limit) {
+    const int v = (int)(((int64_t)x * S + 32768) >> 16);
+    return v < limit - 1 ? v : limit - 1;
+}
+
+__device__ __forceinline__ bool better(int kl_h, int kr_h, int kl_g, int kr_g, int mode) {
+    if (mode == 0) return kl_h > kl_g || (kl_h == kl_g && kr_h > kr_g);
+    return kl_h > kl_g && kr_h > kr_g;
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restrict__ imgs,
+                                                       const CellChunk *__restrict__ chunks,
+                                                       const uint32_t *__restrict__ cell_keys,
+                                                       uint32_t *__restrict__ rank, int pfa, int nms_mode) {
+    constexpr int Q = 2 * R + 1, NS = Q * Q, CENTER = R * Q + R;
+    const CellChunk ch = chunks[blockIdx.x];
+    const ImageDev &im = imgs[ch.image];
+    const LevelDev lv = im.lv[ch.level];
+    const int idx = (int)ch.first + (int)threadIdx.x;
+    if (idx >= lv.ncx * lv.ncy) return;
+    const int64_t g = lv.cell_offset + idx;
+    const uint32_t key = cell_keys[g];
+    if (!key) {
+        rank[g] = 0;
+        return;
+    }
+    const int c = lv.cell, cx = idx % lv.ncx, cy = idx / lv.ncx;
+    const int off = 1023 - (int)(key & 1023u);
+    const int x = cx * c + off % c, y = cy * c + off / c;
+    const int score = (int)((key >> 10) & 0xFFFu);
+    if (!pfa) {
+        rank[g] = (1u << 16) | (uint32_t)score;
+        return;
+    }
+    const int px = project_q16(x, lv.scale_q16, im.w), py = project_q16(y, lv.scale_q16, im.h);
+    int kl[NS], kr[NS];
+#pragma unroll
+    for (int s = 0; s < NS; s++) kl[s] = kr[s] = 0;
+    for (int m = 0; m < im.n_levels; m++) {
+        const LevelDev L = im.lv[m];
+        const float inv = 65536.0f / (float)L.scale_q16;
+        int xlo = (int)floorf(((float)(px - R) - 0.5f) * inv) - 1, xhi = (int)floorf(((float)(px + R) + 0.5f) * inv) + 1;
+        int ylo = (int)floorf(((float)(py - R) - 0.5f) * inv) - 1, yhi = (int)floorf(((float)(py + R) + 0.5f) * inv) + 1;
+        xlo = max(xlo, 0);
+        ylo = max(ylo, 0);
+        xhi = min(xhi, L.w - 1);
+        yhi = min(yhi, L.h - 1);
+        if (xlo > xhi || ylo > yhi) continue;
+        const int cm = L.cell;
+        const int a0 = xlo / cm, a1 = xhi / cm, b0 = ylo / cm, b1 = yhi / cm;
+        for (int bb = b0; bb <= b1; bb++)
+            for (int aa = a0; aa <= a1; aa++) {
+                const uint32_t k = cell_keys[L.cell_offset + (int64_t)bb * L.ncx + aa];
+                if (!k) continue;
+                const int o = 1023 - (int)(k & 1023u);
+                const int qx = project_q16(aa * cm + o % cm, L.scale_q16, im.w) - px;
+                const int qy = project_q16(bb * cm + o / cm, L.scale_q16, im.h) - py;
+                if (qx < -R || qx > R || qy < -R || qy > R) continue;
+                const int slot = (qy + R) * Q + (qx + R);
+                const int sc = (int)((k >> 10) & 0xFFFu);
+#pragma unroll
+                for (int s = 0; s < NS; s++)
+                    if (s == slot) {
+                        kl[s] += 1;
+                        kr[s] += sc;
+                    }
+            }
+    }
+    const int kl_own = kl[CENTER], kr_own = kr[CENTER];
+    bool sup = false;
+#pragma unroll
+    for (int s = 0; s < NS; s++)
+        if (s != CENTER && kl[s] > 0 && better(kl[s], kr[s], kl_own, kr_own, nms_mode)) sup = true;
+    rank[g] = sup ? 0u : (((uint32_t)kl_own << 16) | (uint32_t)kr_own);
+}
+
+constexpr int SEL_THREADS = 1024;
+constexpr int SEL_WAVES = SEL_THREADS / 64;
+
+// Exclusive prefix count of `flag` over the block; returns the prefix and
+// sets *total.  Contains two barriers: every thread must call it.
+__device__ __forceinline__ int block_scan(bool flag, int *wave_cnt, int *total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t bal = __ballot(flag);
+    const int in_wave = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_cnt[wave] = __popcll(bal);
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int w = 0; w < SEL_WAVES; w++) {
+        const int v = wave_cnt[w];
+        before += w < wave ? v : 0;
+        all += v;
+    }
+    __syncthreads();
+    *total = all;
+    return before + in_wave;
+}
+
+__global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
+    const ImageDev *__restrict__ imgs, const uint32_t *__restrict__ cell_keys, const uint32_t *__restrict__ rank,
+    vsfe_kp_soa kps, int32_t *__restrict__ kp_count, int n_max, int32_t *status) {
+    __shared__ int hist[1024];
+    __shared__ int wave_cnt[SEL_WAVES];
+    __shared__ int s_sel[3];   // threshold T, count of ranks > T, bucket
+    const ImageDev &im = imgs[blockIdx.x];
+    const int64_t base = im.cell_base;
+    const int n = (int)im.n_cells;
+    const int tid = threadIdx.x;
+
+    int local = 0;
+    for (int i = tid; i < n; i += SEL_THREADS) local += rank[base + i] != 0;
+    // block sum via the histogram array
+    hist[tid] = local;
+    __syncthreads();
+    for (int s = SEL_THREADS / 2; s > 0; s >>= 1) {
+        if (tid < s) hist[tid] += hist[tid + s];
+        __syncthreads();
+    }
+    const int m = hist[0];
+    __syncthreads();
+
+    uint32_t T = 0;
+    int quota = 0;
+    if (m > n_max) {
+        // pass 1: bucket of the n_max-th largest rank by its high 10 bits (ranks < 2^20)
+        hist[tid] = 0;
+        __syncthreads();
+        for (int i = tid; i < n; i += SEL_THREADS) {
+            const uint32_t v = rank[base + i];
+            if (v) atomicAdd(&hist[v >> 10], 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int bkt = 1023; bkt >= 0; bkt--) {
+                if (acc + hist[bkt] >= n_max) {
+                    s_sel[2] = bkt;
+                    s_sel[1] = acc;
+                    break;
+                }
+                acc += hist[bkt];
+            }
+        }
+        __syncthreads();
+        const int bucket = s_sel[2];
+        hist[tid] = 0;
+        __syncthreads();
+        for (int i = tid; i < n; i += SEL_THREADS) {
+            const uint32_t v = rank[base + i];
+            if (v && (int)(v >> 10) == bucket) atomicAdd(&hist[v & 1023u], 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int acc = s_sel[1];
+            for (int bkt = 1023; bkt >= 0; bkt--) {
+                if (acc + hist[bkt] >= n_max) {
+                    s_sel[0] = (bucket << 10) | bkt;
+                    s_sel[1] = acc;
+                    break;
+                }
+                acc += hist[bkt];
+            }
+        }
+        __syncthreads();
+        T = (uint32_t)s_sel[0];
+        quota = n_max - s_sel[1];
+    }
+
+    // compaction in canonical order
+    int running = 0, eq_running = 0;
+    for (int start = 0; start < n; start += SEL_THREADS) {
+        const int i = start + tid;
+        const uint32_t v = i < n ? rank[base + i] : 0u;
+        int eq_total, keep_total;
+        const bool is_eq = v != 0 && T != 0 && v == T;
+        const int eq_before = block_scan(is_eq, wave_cnt, &eq_total) + eq_running;
+        const bool keep = v != 0 && (v > T || (is_eq && eq_before < quota));
+        const int slot = block_scan(keep, wave_cnt, &keep_total) + running;
+        if (keep) {
+            int l = 0;
+            while (l + 1 < im.n_levels && im.lv[l + 1].cell_offset - base <= i) l++;
+            const LevelDev &lv = im.lv[l];
+            const int li = (int)(i - (lv.cell_offset - base));
+            const uint32_t key = cell_keys[base + i];
+            const int c = lv.cell, cx = li % lv.ncx, cy = li / lv.ncx;
+            const int off = 1023 - (int)(key & 1023u);
+            const int x = cx * c + off % c, y = cy * c + off / c;
+            if (slot < n_max) {
+                const int64_t o = im.kp_offset + slot;
+                kps.x[o] = (uint16_t)x;
+                kps.y[o] = (uint16_t)y;
+                kps.level[o] = (uint8_t)l;
+                kps.flags[o] = (key & VSFE_KEY_FALLBACK) ? (uint8_t)VSFE_KP_FALLBACK : (uint8_t)0;
+                kps.score[o] = (uint16_t)((key >> 10) & 0xFFFu);
+                kps.x0[o] = (uint16_t)project_q16(x, lv.scale_q16, im.w);
+                kps.y0[o] = (uint16_t)project_q16(y, lv.scale_q16, im.h);
+                kps.kl[o] = (uint8_t)(v >> 16);
+                kps.kr[o] = v & 0xFFFFu;
+                kps.bin[o] = 0;
+            } else if (status) {
+                atomicOr(status, VSFE_DEV_OVERFLOW);
+            }
+        }
+        running += keep_total;
+        eq_running += eq_total;
+    }
+    if (tid == 0) kp_count[blockIdx.x] = running < n_max ? running : n_max;
+}
+
+}  // namespace vsfe
+
+using namespace vsfe;
+
+extern "C" int32_t pyca_cull_aggregate(const vsfe_ctx *ctx, const vsfe_batch *b, const uint32_t *cell_keys,
+                                       void *workspace, const vsfe_kp_soa *kps, int32_t *kp_count,
+                                       int32_t *status, void *stream) {
+    int32_t rc = check_common(ctx, b, status);
+    if (rc) return rc;
+    if (!cell_keys || !workspace || !kps || !kp_count) return fail(VSFE_EINVAL, "null buffer");
+    if (!kps->x || !kps->y || !kps->level || !kps->flags || !kps->score || !kps->x0 || !kps->y0 || !kps->kl ||
+        !kps->kr || !kps->bin)
+        return fail(VSFE_EINVAL, "null keypoint array");
+    const vsfe_params &p = ctx->p;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *rank = (uint32_t *)workspace;
+    if (b->n_chunks > 0) {
+        switch (p.nms_radius) {
+            case 0:
+                hipLaunchKernelGGL(pfa_eval_kernel<0>, dim3(b->n_chunks), dim3(256), 0, st, b->d_images, b->d_chunks,
+                                   cell_keys, rank, p.pfa, p.nms_mode);
+                break;
+            case 1:
+                hipLaunchKernelGGL(pfa_eval_kernel<1>, dim3(b->n_chunks), dim3(256), 0, st, b->d_images, b->d_chunks,
+                                   cell_keys, rank, p.pfa, p.nms_mode);
+                break;
+            case 2:
+                hipLaunchKernelGGL(pfa_eval_kernel<2>, dim3(b->n_chunks), dim3(256), 0, st, b->d_images, b->d_chunks,
+                                   cell_keys, rank, p.pfa, p.nms_mode);
+                break;
+            default:
+                hipLaunchKernelGGL(pfa_eval_kernel<3>, dim3(b->n_chunks), dim3(256), 0, st, b->d_images, b->d_chunks,
+                                   cell_keys, rank, p.pfa, p.nms_mode);
+                break;
+        }
+        rc = check_launch("pyca_cull_aggregate (aggregation)");
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(select_compact_kernel, dim3(b->n_images), dim3(SEL_THREADS), 0, st, b->d_images, cell_keys,
+                       rank, *kps, kp_count, p.n_max, status);
+    return check_launch("pyca_cull_aggregate (select)");
+}

@@ -1,0 +1,113 @@
+// Stereo matching along rectified rows by descriptor-distance minimisation
+// (Sec. III-3, the middle-end's stereo matcher).
+//
+// One thread per left keypoint.  Right keypoints are stored in canonical
+// order (level, cell row, cell column), so the candidates of a left
+// keypoint at level l and row y -- same level, |dy| <= row_band -- lie in
+// the contiguous run of cell rows floor((y - band) / c_l) ..
+// floor((y + band) / c_l), found by two binary searches.  Each candidate
+// with native-scale disparity d = x0_l - x0_r in [0, d_max] costs eight
+// popcounts; the least distance wins, ties to smaller |dy|, smaller d,
+// smaller index (ascending scan with strict comparisons).
+#include "vsfe_internal.h"
+
+namespace vsfe {
+
+struct StereoArgs {
+    int cell[VSFE_MAX_LEVELS];
+    int n_max, n_pairs, d_max, match_th, band;
+};
+
+__device__ __forceinline__ int row_key(int level, int y, const StereoArgs &a) { return (level << 16) | (y / a.cell[level]); }
+
+__global__ __launch_bounds__(256) void stereo_kernel(const ImageDev *__restrict__ imgs, vsfe_kp_soa kps,
+                                                     const int32_t *__restrict__ kp_count,
+                                                     const uint32_t *__restrict__ desc, int32_t *__restrict__ midx,
+                                                     uint16_t *__restrict__ mdist, int16_t *__restrict__ mdisp,
+                                                     StereoArgs a) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int pair = (int)(s / a.n_max);
+    const int i = (int)(s - (int64_t)pair * a.n_max);
+    if (pair >= a.n_pairs) return;
+    const int li = 2 * pair, ri = 2 * pair + 1;
+    if (i >= kp_count[li]) return;
+    const int64_t lslot = imgs[li].kp_offset + i;
+    const int64_t rbase = imgs[ri].kp_offset;
+    const int nr = kp_count[ri];
+    const int level = kps.level[lslot], y = kps.y[lslot], x0 = kps.x0[lslot];
+    uint32_t d[8];
+#pragma unroll
+    for (int w = 0; w < 8; w++) d[w] = desc[lslot * 8 + w];
+
+    const int klo = row_key(level, max(y - a.band, 0), a), khi = row_key(level, y + a.band, a);
+    // first index with key >= klo
+    int lo = 0, hi = nr;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (row_key(kps.level[rbase + mid], kps.y[rbase + mid], a) < klo) lo = mid + 1;
+        else hi = mid;
+    }
+    const int start = lo;
+    hi = nr;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (row_key(kps.level[rbase + mid], kps.y[rbase + mid], a) <= khi) lo = mid + 1;
+        else hi = mid;
+    }
+    const int end = lo;
+
+    int best = -1, bd = 0, bdy = 0, bdisp = 0;
+    for (int j = start; j < end; j++) {
+        const int64_t rs = rbase + j;
+        int dy = (int)kps.y[rs] - y;
+        dy = dy < 0 ? -dy : dy;
+        if (dy > a.band) continue;
+        const int dd = x0 - (int)kps.x0[rs];
+        if (dd < 0 || dd > a.d_max) continue;
+        int h = 0;
+#pragma unroll
+        for (int w = 0; w < 8; w++) h += __popc(d[w] ^ desc[rs * 8 + w]);
+        if (best < 0 || h < bd || (h == bd && (dy < bdy || (dy == bdy && dd < bdisp)))) {
+            best = j;
+            bd = h;
+            bdy = dy;
+            bdisp = dd;
+        }
+    }
+    const int64_t o = (int64_t)pair * a.n_max + i;
+    if (best >= 0 && bd <= a.match_th) {
+        midx[o] = best;
+        mdist[o] = (uint16_t)bd;
+        mdisp[o] = (int16_t)bdisp;
+    } else {
+        midx[o] = -1;
+        mdist[o] = 0xFFFF;
+        mdisp[o] = -1;
+    }
+}
+
+}  // namespace vsfe
+
+using namespace vsfe;
+
+extern "C" int32_t stereo_match(const vsfe_ctx *ctx, const vsfe_batch *b, const vsfe_kp_soa *kps,
+                                const int32_t *kp_count, const uint32_t *desc, int32_t *match_idx,
+                                uint16_t *match_dist, int16_t *match_disp, int32_t *status, void *stream) {
+    int32_t rc = check_common(ctx, b, status);
+    if (rc) return rc;
+    if (!kps || !kp_count || !desc || !match_idx || !match_dist || !match_disp) return fail(VSFE_EINVAL, "null buffer");
+    if (!kps->y || !kps->level || !kps->x0) return fail(VSFE_EINVAL, "null keypoint array");
+    if (!b->pairs_ok) return fail(VSFE_EINVAL, "stereo_match needs pairs of equal-size images (2i, 2i+1)");
+    StereoArgs a;
+    for (int l = 0; l < VSFE_MAX_LEVELS; l++) a.cell[l] = ctx->cell[l] > 0 ? ctx->cell[l] : 1;
+    a.n_max = ctx->p.n_max;
+    a.n_pairs = b->n_images / 2;
+    a.d_max = ctx->p.d_max;
+    a.match_th = ctx->p.match_th;
+    a.band = ctx->p.row_band;
+    const int64_t n = (int64_t)a.n_pairs * a.n_max;
+    if (n <= 0) return VSFE_OK;
+    hipLaunchKernelGGL(stereo_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       b->d_images, *kps, kp_count, desc, match_idx, match_dist, match_disp, a);
+    return check_launch("stereo_match");
+}

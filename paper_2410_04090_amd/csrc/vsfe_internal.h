@@ -1,0 +1,100 @@
+// Internal declarations of the gfx950 front-end library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "vsfe.h"
+
+namespace vsfe {
+
+// Per-level geometry as the kernels see it (one 64-byte record).
+struct LevelDev {
+    int32_t w, h, pitch, cell;
+    int32_t ncx, ncy, scale_q16, pad;
+    int64_t offset;        // level 0: into the input buffer, else into the pyramid buffer
+    int64_t cell_offset;   // global index of the first cell of this level
+    int64_t crf_offset;    // first element of this level in the response dump
+};
+static_assert(sizeof(LevelDev) == 56, "LevelDev layout");
+
+struct ImageDev {
+    int32_t w, h, n_levels, pad;
+    int64_t cell_base;     // first cell of the image (level 0)
+    int64_t n_cells;       // cells over all levels
+    int64_t cell0_offset;  // first level-0 cell in mask / logit arrays
+    int64_t kp_offset;     // first keypoint slot
+    LevelDev lv[VSFE_MAX_LEVELS];
+};
+
+// Output tile of the pyramid kernel: PYR_TW x PYR_TH pixels of one level.
+constexpr int PYR_TW = 64;
+constexpr int PYR_TH = 16;
+struct PyrItem {
+    uint16_t image, tx, ty, pad;
+};
+
+// Detector work item: a rectangle of whole cells of one level.
+struct DetItem {
+    uint16_t image, level, cx0, cy0, nkx, nky, pad0, pad1;
+};
+
+// Aggregation work item: PYCA_CHUNK consecutive cells of one level.
+constexpr int PYCA_CHUNK = 256;
+struct CellChunk {
+    uint16_t image, level;
+    uint32_t first;        // cell index within the level
+};
+
+// Rotation and bin tables (Q14) of the orientation and rBRIEF steps.
+struct OrbTables {
+    int32_t bin_x[30], bin_y[30];
+};
+
+}  // namespace vsfe
+
+struct vsfe_ctx {
+    vsfe_params p;
+    int device;
+    int tile_w, tile_h;
+    int8_t *d_pattern_rot;     // [30][256][4] rotated test pairs (device)
+    vsfe::OrbTables tables;    // host copy, passed by value to kernels
+    int32_t scale_q16[VSFE_MAX_LEVELS];
+    int32_t cell[VSFE_MAX_LEVELS];
+};
+
+struct vsfe_batch {
+    const vsfe_ctx *ctx = nullptr;
+    int32_t n_images = 0;
+    vsfe_batch_info info{};
+    std::vector<vsfe::ImageDev> images;          // host copy
+    vsfe::ImageDev *d_images = nullptr;          // device copy
+    // pyramid work: items of level l are [pyr_start[l], pyr_start[l+1])
+    std::vector<int32_t> pyr_start;
+    std::vector<vsfe::PyrItem> h_pyr_items;
+    vsfe::PyrItem *d_pyr_items = nullptr;
+    int32_t n_det_items = 0;
+    std::vector<vsfe::DetItem> h_det_items;
+    vsfe::DetItem *d_det_items = nullptr;
+    int32_t n_chunks = 0;
+    std::vector<vsfe::CellChunk> h_chunks;
+    vsfe::CellChunk *d_chunks = nullptr;
+    bool pairs_ok = false;                       // even count, equal pair sizes
+};
+
+namespace vsfe {
+
+void set_error(const std::string &msg);
+int32_t fail(int32_t code, const std::string &msg);
+int32_t check_launch(const char *what);
+int32_t check_common(const vsfe_ctx *ctx, const vsfe_batch *b, int32_t *status);
+
+// level geometry shared by the host planner
+void level_size(int32_t W, int32_t H, int32_t l, int32_t *Wl, int32_t *Hl);
+int32_t cell_size(int32_t cell0, int32_t l);
+int32_t scale_q16(int32_t l);
+
+}  // namespace vsfe

@@ -1,0 +1,166 @@
+"""Batch front-end: owns the library context, the batch object and the
+device buffers, and issues the five C-ABI calls on one stream.
+
+Memory comes from PyTorch (device tensors); every computation is a kernel
+of libvsfe.so.  ``run()`` only launches kernels, so it can be captured into
+a HIP graph (``capture()`` / ``replay()``).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import vsfe
+
+
+def _round_up(v, a):
+    return (v + a - 1) // a * a
+
+
+class Frontend:
+    def __init__(self, params, sizes, pattern, device="cuda", tile=None, with_crf=False,
+                 with_mask=False):
+        self.params = vsfe.make_params(params)
+        self.sizes = [(int(w), int(h)) for (w, h) in sizes]
+        self.n = len(self.sizes)
+        self.device = torch.device(device)
+        self.ctx = vsfe.ctx_create(self.params, pattern)
+        if tile is not None:
+            vsfe.ctx_set_tile(self.ctx, *tile)
+        self.pitches = [_round_up(w, 64) for (w, _) in self.sizes]
+        self.offsets, at = [], 0
+        for (w, h), pt in zip(self.sizes, self.pitches):
+            self.offsets.append(at)
+            at = _round_up(at + pt * h, 256)
+        self.batch = vsfe.batch_create(self.ctx, [w for w, _ in self.sizes], [h for _, h in self.sizes],
+                                       self.pitches, self.offsets)
+        info = vsfe.batch_info(self.batch)
+        self.info = info
+        dev = self.device
+        u8 = dict(dtype=torch.uint8, device=dev)
+        i32 = dict(dtype=torch.int32, device=dev)
+        self.images = torch.zeros(max(info.input_bytes, 1), **u8)
+        self.pyr = torch.zeros(max(info.pyr_bytes, 1), **u8)
+        self.cell_keys = torch.zeros(max(info.n_cells, 1), **i32)
+        self.workspace = torch.zeros(max(info.workspace_bytes, 1), **u8)
+        cap = max(info.kp_capacity, 1)
+        self.kps = {n: torch.zeros(cap, dtype=t, device=dev) for n, t in vsfe.KP_FIELDS}
+        self.kp_count = torch.zeros(self.n, **i32)
+        self.desc = torch.zeros(cap * 8, **i32)
+        mcap = max(info.match_capacity, 1)
+        self.match_idx = torch.zeros(mcap, **i32)
+        self.match_dist = torch.zeros(mcap, dtype=torch.int16, device=dev)
+        self.match_disp = torch.zeros(mcap, dtype=torch.int16, device=dev)
+        self.status = torch.zeros(1, **i32)
+        self.crf = torch.zeros(max(info.crf_elems, 1), dtype=torch.int16, device=dev) if with_crf else None
+        self.cell_mask = torch.ones(max(info.n_cells0, 1), **u8) if with_mask else None
+        self.describe = True
+        self.stereo = self.n % 2 == 0 and all(self.sizes[i] == self.sizes[i + 1] for i in range(0, self.n, 2))
+        self._graph = None
+
+    # ------------------------------------------------------------ data in/out
+    def pack(self, imgs) -> torch.Tensor:
+        """Pack host uint8 images into one pinned host buffer (input layout)."""
+        host = torch.zeros(self.images.numel(), dtype=torch.uint8, pin_memory=True)
+        hv = host.numpy()
+        for img, (w, h), pt, off in zip(imgs, self.sizes, self.pitches, self.offsets):
+            assert img.shape == (h, w) and img.dtype == np.uint8
+            hv[off:off + pt * h].reshape(h, pt)[:, :w] = img
+        return host
+
+    def upload(self, imgs):
+        self.images.copy_(self.pack(imgs), non_blocking=False)
+
+    def level_info(self, i, l):
+        return vsfe.batch_level_info(self.batch, i, l)
+
+    # ------------------------------------------------------------ pipeline
+    def run(self, stream=None, mask=None, describe=None, stereo=None):
+        describe = self.describe if describe is None else describe
+        stereo = self.stereo if stereo is None else stereo
+        c, b = self.ctx, self.batch
+        vsfe.pyramid_build(c, b, self.images, self.pyr, self.status, stream)
+        vsfe.fast_br_detect(c, b, self.images, self.pyr, mask, self.cell_keys, self.crf, self.status, stream)
+        vsfe.pyca_cull_aggregate(c, b, self.cell_keys, self.workspace, self.kps, self.kp_count, self.status,
+                                 stream)
+        if describe:
+            vsfe.orb_describe(c, b, self.images, self.pyr, self.kps, self.kp_count, self.desc, self.status, stream)
+            if stereo:
+                vsfe.stereo_match(c, b, self.kps, self.kp_count, self.desc, self.match_idx, self.match_dist,
+                                  self.match_disp, self.status, stream)
+
+    def capture(self, **kw):
+        """Capture run() into a HIP graph on a side stream."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run(stream=s, **kw)          # warm-up outside the graph
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self.run(stream=s, **kw)
+        torch.cuda.synchronize()
+        self._graph = g
+        return g
+
+    def replay(self):
+        self._graph.replay()
+
+    # ------------------------------------------------------------ results
+    def results(self, image):
+        """Keypoints (+ descriptors) of one image as numpy arrays (synchronises)."""
+        n = int(self.kp_count[image].item())
+        base = image * self.params.n_max
+        out = {}
+        for name, t in vsfe.KP_FIELDS:
+            a = self.kps[name][base:base + n].cpu().numpy()
+            if name in ("x", "y", "score", "x0", "y0"):
+                a = a.view(np.uint16)
+            elif name == "kr":
+                a = a.view(np.uint32)
+            out[name] = a
+        out["desc"] = self.desc[base * 8:(base + n) * 8].cpu().numpy().view(np.uint32).reshape(n, 8)
+        return out
+
+    def matches(self, pair):
+        n = int(self.kp_count[2 * pair].item())
+        base = pair * self.params.n_max
+        return (self.match_idx[base:base + n].cpu().numpy(),
+                self.match_dist[base:base + n].cpu().numpy().view(np.uint16),
+                self.match_disp[base:base + n].cpu().numpy())
+
+    def pyramid_levels(self, image):
+        """Levels 0..L-1 of one image as numpy arrays."""
+        out = []
+        for l in range(self.params.n_levels):
+            li = self.level_info(image, l)
+            src = self.images if l == 0 else self.pyr
+            flat = src[li.offset:li.offset + li.pitch * li.height].cpu().numpy()
+            out.append(flat.reshape(li.height, li.pitch)[:, :li.width].copy())
+        return out
+
+    def cell_keys_level(self, image, level):
+        li = self.level_info(image, level)
+        n = li.ncx * li.ncy
+        a = self.cell_keys[li.cell_offset:li.cell_offset + n].cpu().numpy().view(np.uint32)
+        return a.reshape(li.ncy, li.ncx)
+
+    def crf_level(self, image, level):
+        li = self.level_info(image, level)
+        a = self.crf[li.crf_offset:li.crf_offset + li.width * li.height].cpu().numpy().view(np.uint16)
+        return a.reshape(li.height, li.width)
+
+    def close(self):
+        if self.batch is not None:
+            vsfe.batch_destroy(self.batch)
+            self.batch = None
+        if self.ctx is not None:
+            vsfe.ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

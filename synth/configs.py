@@ -23,6 +23,7 @@ class Params:
     cell0: int = 32         # level-0 cell size
     pfa: int = 1            # pyramidal feature aggregation on/off
     nms_mode: int = 0       # 0 = lexicographic (k_l, k_r), 1 = both strictly larger
+    nms_radius: int = 1     # NMS window q = 2 r + 1 at the native scale
     n_max: int = 2000       # keypoints kept per image
     blur: int = 1           # smooth before rBRIEF sampling
     d_max: int = 96         # stereo disparity search range at level 0

@@ -1,0 +1,181 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every stage is compared element by element on seeded inputs: pyramid
+levels, per-cell keys (with the fallback flag), the response dump, the
+aggregated keypoint lists, orientation bins, descriptors and matches.
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs, scenes
+from synth.configs import Params
+from tests.parity_util import (compare_cells, compare_crf, compare_kps, compare_matches,
+                               compare_pyramid, oracle_image, say)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fe_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_04090_amd import frontend
+    return frontend
+
+
+def run_and_compare(fe_mod, imgs, params, pattern, full_stages=True, tile=None, mask=None, describe=True):
+    sizes = [(im.shape[1], im.shape[0]) for im in imgs]
+    say("case: sizes=%s params=%s tile=%s mask=%s" % (sizes[:4], params, tile, mask is not None))
+    fe = fe_mod.Frontend(params, sizes, pattern, tile=tile, with_crf=full_stages,
+                         with_mask=mask is not None)
+    try:
+        fe.upload(imgs)
+        mt = None
+        if mask is not None:
+            import torch
+            fe.cell_mask.copy_(torch.from_numpy(np.concatenate([m.reshape(-1) for m in mask])))
+            mt = fe.cell_mask
+        fe.run(mask=mt, describe=describe and params.border >= 15)
+        import torch
+        torch.cuda.synchronize()
+        assert int(fe.status.item()) == 0
+        refs = []
+        for i, img in enumerate(imgs):
+            if full_stages:
+                levels = compare_pyramid(fe, i, img, params)
+                if mask is None:
+                    compare_cells(fe, i, levels, params)
+                compare_crf(fe, i, levels, params)
+            _, ref = oracle_image(img, params, pattern, None if mask is None else mask[i])
+            got = fe.results(i)
+            compare_kps(ref, got, i, describe=describe and params.border >= 15)
+            refs.append(ref)
+        n_acc = 0
+        if describe and params.border >= 15 and fe.stereo:
+            for pr in range(len(imgs) // 2):
+                n_acc += compare_matches(fe, pr, refs[2 * pr], refs[2 * pr + 1], params)
+        return fe, refs, n_acc
+    finally:
+        fe.close()
+
+
+def test_cfg1_mono_752x480(fe_mod, pattern):
+    w = configs.cfg1()
+    imgs = w.images()
+    _, refs, _ = run_and_compare(fe_mod, imgs, w.params, pattern, describe=False)
+    assert len(refs[0]["x"]) > 100
+
+
+def test_cfg2_pair_1241x376(fe_mod, pattern):
+    w = configs.cfg2()
+    _, refs, n_acc = run_and_compare(fe_mod, w.images(), w.params, pattern)
+    assert len(refs[0]["x"]) > 500 and n_acc > 100
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_random_dense_pairs_with_cap(fe_mod, pattern, seed):
+    """Uniform noise: a corner in almost every cell, so the cap binds."""
+    a = scenes.random_image(seed, 257, 193)
+    b = scenes.random_image(seed + 100, 257, 193)
+    p = Params(n_max=150)
+    _, refs, _ = run_and_compare(fe_mod, [a, b], p, pattern)
+    assert len(refs[0]["x"]) == 150
+
+
+@pytest.mark.parametrize("W,H", [(97, 61), (130, 77), (33, 33), (640, 17)])
+def test_ragged_and_tiny_sizes(fe_mod, pattern, W, H):
+    """Odd sizes, partial cells, and levels narrower than twice the border."""
+    l, r = scenes.stereo_pair(50 + W, W, H, 30, 10)
+    run_and_compare(fe_mod, [l, r], Params(), pattern)
+
+
+def test_flat_images_no_keypoints(fe_mod, pattern):
+    img = np.full((120, 160), 128, np.uint8)
+    _, refs, _ = run_and_compare(fe_mod, [img, img.copy()], Params(), pattern)
+    assert len(refs[0]["x"]) == 0
+
+
+@pytest.mark.parametrize("variant", [
+    dict(nms_mode=1), dict(nms_radius=0), dict(nms_radius=2), dict(nms_radius=3),
+    dict(p_max=16, eps_lo=-1), dict(pfa=0, n_max=5000), dict(blur=0), dict(eps_hi=35, eps_lo=12),
+    dict(cell0=16, n_levels=6), dict(p_min=12, p_max=14), dict(row_band=0, d_max=40, match_th=90),
+])
+def test_parameter_variants(fe_mod, pattern, variant):
+    l, r = scenes.stereo_pair(77, 420, 260, 90, 40)
+    p = replace(Params(), **variant)
+    run_and_compare(fe_mod, [l, r], p, pattern)
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (32, 16), (128, 64), (96, 40)])
+def test_tile_shapes_identical(fe_mod, pattern, tile):
+    l, r = scenes.stereo_pair(78, 333, 201, 80, 40)
+    run_and_compare(fe_mod, [l, r], Params(), pattern, tile=tile)
+
+
+def test_mixed_batch(fe_mod, pattern):
+    """Pairs of four sizes in one batch (the mixed-resolution workload at
+    reduced scale)."""
+    imgs = []
+    for k, (w, h) in enumerate([(320, 240), (376, 240), (620, 188), (640, 360)]):
+        l, r = scenes.stereo_pair(300 + k, w, h, 80, 40)
+        imgs += [l, r]
+    run_and_compare(fe_mod, imgs, Params(), pattern)
+
+
+def test_gated_detection_matches_oracle(fe_mod, pattern):
+    """Learned gating: a random level-0 cell mask applied on both sides."""
+    l, r = scenes.stereo_pair(91, 400, 300, 100, 40)
+    p = Params()
+    rng = np.random.default_rng(5)
+    ncx, ncy = (400 + 31) // 32, (300 + 31) // 32
+    masks = [(rng.random((ncy, ncx)) < 0.4).astype(np.uint8) for _ in range(2)]
+    run_and_compare(fe_mod, [l, r], p, pattern, full_stages=False, mask=masks)
+
+
+def test_deterministic_repeats(fe_mod, pattern):
+    import torch
+    w = configs.cfg2()
+    imgs = w.images()
+    fe = fe_mod.Frontend(w.params, [(1241, 376)] * 2, pattern)
+    try:
+        fe.upload(imgs)
+        outs = []
+        for _ in range(3):
+            fe.run()
+            torch.cuda.synchronize()
+            outs.append([fe.results(0)["desc"].copy(), fe.matches(0)[0].copy()])
+        for o in outs[1:]:
+            assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+    finally:
+        fe.close()
+
+
+def test_graph_replay_matches_eager(fe_mod, pattern):
+    import torch
+    w = configs.cfg2()
+    imgs = w.images()
+    fe = fe_mod.Frontend(w.params, [(1241, 376)] * 2, pattern)
+    try:
+        fe.upload(imgs)
+        fe.run()
+        torch.cuda.synchronize()
+        eager = (fe.results(0), fe.results(1), fe.matches(0))
+        fe.capture()
+        for rep in range(3):
+            fe.kp_count.zero_()
+            fe.desc.zero_()
+            torch.cuda.synchronize()
+            fe.replay()
+            torch.cuda.synchronize()
+            got = (fe.results(0), fe.results(1), fe.matches(0))
+            for a, b in zip(eager[:2], got[:2]):
+                for k in a:
+                    assert np.array_equal(a[k], b[k]), (rep, k)
+            for a, b in zip(eager[2], got[2]):
+                assert np.array_equal(a, b)
+    finally:
+        fe.close()
