@@ -162,7 +162,7 @@ int32_t vsfe_batch_level_info(const vsfe_batch *b, int32_t image, int32_t level,
 /* Tile shape of fast_br_detect: the target tile extent in pixels (each
  * level packs as many whole cells as fit, at least one).  Host only; takes
  * effect for batches created afterwards.  EINVAL unless 8 <= tw <= 128,
- * 8 <= th <= 64. */
+ * 8 <= th <= 32. */
 int32_t vsfe_ctx_set_tile(vsfe_ctx *ctx, int32_t tile_w, int32_t tile_h);
 
 /* Last error message of the calling thread ("" if none). */

@@ -133,16 +133,77 @@ static int32_t plan_batch(const vsfe_params &p, int tile_w, int tile_h, int32_t 
         im.n_cells = cell_at - im.cell_base;
         cell0_at += (int64_t)im.lv[0].ncx * im.lv[0].ncy;
     }
-    // pyramid tiles, level-major so that one launch covers one level of all images
+    // resampling tables, one per distinct (source size, level): entry o holds
+    // the floored Q8 source coordinate of output o (index | weight << 16),
+    // weight forced to 0 where the right / bottom neighbour is clamped
+    b->h_coord.clear();
+    b->aligned_input = true;
+    b->aligned_input16 = true;
+    for (int i = 0; i < n; i++) {
+        if ((pitches[i] & 3) || (offsets[i] & 3)) b->aligned_input = false;
+        if ((pitches[i] & 15) || (offsets[i] & 15)) b->aligned_input16 = false;
+    }
+    auto q8 = [](int64_t o, int64_t n_src, int64_t n_dst, int *a, int *f) {
+        const int64_t t = ((2 * o + 1) * n_src - n_dst) * 128 / n_dst;
+        *a = (int)(t >> 8);
+        *f = (int)(t & 255);
+        if (*a + 1 >= n_src) *f = 0;
+    };
+    std::vector<std::pair<std::pair<int, int>, int>> seen;   // ((W, H), image with its tables)
+    for (int i = 0; i < n; i++) {
+        ImageDev &im = b->images[i];
+        int from = -1;
+        for (auto &sv : seen)
+            if (sv.first.first == im.w && sv.first.second == im.h) from = sv.second;
+        if (from >= 0) {
+            for (int l = 1; l < L; l++) {
+                im.lv[l].xtab = b->images[from].lv[l].xtab;
+                im.lv[l].ytab = b->images[from].lv[l].ytab;
+            }
+            continue;
+        }
+        seen.push_back({{im.w, im.h}, i});
+        for (int l = 1; l < L; l++) {
+            const LevelDev &s = im.lv[l - 1];
+            LevelDev &d = im.lv[l];
+            d.xtab = (int32_t)b->h_coord.size();
+            for (int o = 0; o < d.w; o++) {
+                int a, f;
+                q8(o, s.w, d.w, &a, &f);
+                b->h_coord.push_back((uint32_t)a | ((uint32_t)f << 16));
+            }
+            d.ytab = (int32_t)b->h_coord.size();
+            for (int o = 0; o < d.h; o++) {
+                int a, f;
+                q8(o, s.h, d.h, &a, &f);
+                b->h_coord.push_back((uint32_t)a | ((uint32_t)f << 16));
+            }
+        }
+    }
+    // pyramid tiles, level-major so that one launch covers one level of all
+    // images; each records the source window it reads
     b->pyr_start.assign(L + 1, 0);
     b->h_pyr_items.clear();
     for (int l = 1; l < L; l++) {
         b->pyr_start[l] = (int32_t)b->h_pyr_items.size();
         for (int i = 0; i < n; i++) {
+            const LevelDev &s = b->images[i].lv[l - 1];
             const LevelDev &lv = b->images[i].lv[l];
             for (int ty = 0; ty < (lv.h + PYR_TH - 1) / PYR_TH; ty++)
-                for (int tx = 0; tx < (lv.w + PYR_TW - 1) / PYR_TW; tx++)
-                    b->h_pyr_items.push_back(PyrItem{(uint16_t)i, (uint16_t)tx, (uint16_t)ty, 0});
+                for (int tx = 0; tx < (lv.w + PYR_TW - 1) / PYR_TW; tx++) {
+                    const int ox0 = tx * PYR_TW, ox1 = std::min(lv.w, ox0 + PYR_TW) - 1;
+                    const int oy0 = ty * PYR_TH, oy1 = std::min(lv.h, oy0 + PYR_TH) - 1;
+                    const int xa0 = (int)(b->h_coord[lv.xtab + ox0] & 0xFFFF) & ~15;
+                    const int xa1 = (int)(b->h_coord[lv.xtab + ox1] & 0xFFFF) + 1;
+                    const int ya0 = (int)(b->h_coord[lv.ytab + oy0] & 0xFFFF);
+                    const int ya1 = (int)(b->h_coord[lv.ytab + oy1] & 0xFFFF) + 1;
+                    const int ncols = ((xa1 - xa0 + 1) + 15) & ~15, nrows = ya1 - ya0 + 1;
+                    if (ncols > PYR_SW || nrows > PYR_SH)
+                        return fail(VSFE_ECAPACITY, "pyramid source window exceeds the staging buffer");
+                    (void)s;
+                    b->h_pyr_items.push_back(PyrItem{(uint16_t)i, (uint16_t)tx, (uint16_t)ty, 0, (uint16_t)xa0,
+                                                     (uint16_t)ya0, (uint16_t)ncols, (uint16_t)nrows});
+                }
         }
     }
     b->pyr_start[L] = (int32_t)b->h_pyr_items.size();
@@ -261,10 +322,12 @@ int32_t vsfe_ctx_create(const vsfe_params *p, const int8_t *pattern, vsfe_ctx **
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(VSFE_EUNSUPPORTED, std::string("library built for gfx950, device is ") + prop.gcnArchName);
 
+    rc = orb_prepare(dev);
+    if (rc) return rc;
     vsfe_ctx *c = new vsfe_ctx();
     c->p = *p;
     c->device = dev;
-    c->tile_w = 64;
+    c->tile_w = 128;
     c->tile_h = 32;
     for (int l = 0; l < VSFE_MAX_LEVELS; l++) {
         c->scale_q16[l] = scale_q16(l);
@@ -316,7 +379,7 @@ int32_t vsfe_ctx_destroy(vsfe_ctx *ctx) {
 
 int32_t vsfe_ctx_set_tile(vsfe_ctx *ctx, int32_t tile_w, int32_t tile_h) {
     if (!ctx) return fail(VSFE_EINVAL, "null context");
-    if (tile_w < 8 || tile_w > 128 || tile_h < 8 || tile_h > 64) return fail(VSFE_EINVAL, "tile out of range");
+    if (tile_w < 8 || tile_w > 128 || tile_h < 8 || tile_h > 32) return fail(VSFE_EINVAL, "tile out of range");
     ctx->tile_w = tile_w;
     ctx->tile_h = tile_h;
     return VSFE_OK;
@@ -326,6 +389,7 @@ int32_t vsfe_batch_destroy(vsfe_batch *b) {
     if (!b) return VSFE_OK;
     if (b->d_images) (void)hipFree(b->d_images);
     if (b->d_pyr_items) (void)hipFree(b->d_pyr_items);
+    if (b->d_coord) (void)hipFree(b->d_coord);
     if (b->d_det_items) (void)hipFree(b->d_det_items);
     if (b->d_chunks) (void)hipFree(b->d_chunks);
     delete b;
@@ -337,7 +401,7 @@ int32_t vsfe_batch_plan(const vsfe_params *p, int32_t n, const int32_t *widths,
                         vsfe_batch_info *out) {
     if (!p || !out) return fail(VSFE_EINVAL, "null argument");
     vsfe_batch tmp;
-    int32_t rc = plan_batch(*p, 64, 32, n, widths, heights, pitches, offsets, &tmp);
+    int32_t rc = plan_batch(*p, 128, 32, n, widths, heights, pitches, offsets, &tmp);
     if (rc) return rc;
     *out = tmp.info;
     return VSFE_OK;
@@ -354,6 +418,7 @@ int32_t vsfe_batch_create(const vsfe_ctx *ctx, int32_t n, const int32_t *widths,
     int32_t rc = plan_batch(ctx->p, ctx->tile_w, ctx->tile_h, n, widths, heights, pitches, offsets, b);
     if (!rc) rc = upload(b->images, &b->d_images);
     if (!rc) rc = upload(b->h_pyr_items, &b->d_pyr_items);
+    if (!rc) rc = upload(b->h_coord, &b->d_coord);
     if (!rc) rc = upload(b->h_det_items, &b->d_det_items);
     if (!rc) rc = upload(b->h_chunks, &b->d_chunks);
     if (rc) {

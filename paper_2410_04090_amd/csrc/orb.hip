@@ -2,78 +2,136 @@
 // (Sec. III-2: Gaussian smoothing, then extraction for every scale at once).
 //
 // One 64-lane wave per keypoint.  The wave stages the 37 x 37 neighbourhood
-// of its keypoint in LDS (coordinates clamped to the level, which makes the
-// clamp-to-edge smoothing exact), then
-//   * intensity centroid m10 = sum u I, m01 = sum v I over u^2 + v^2 <= 225
-//     on the unsmoothed level, reduced across the wave;
-//   * orientation bin: 30 lanes compare m with the Q14 bin boundaries at
-//     6 + 12 j degrees by exact integer half-plane / cross-product tests,
-//     a ballot counts them (bin = count mod 30, 0 for m = 0);
-//   * smoothing only of the 31 x 31 patch the tests can touch, separable
-//     7-tap [18 33 49 56 49 33 18] / 256, each pass rounded half up;
-//   * 256 tests on the bin-rotated pattern (precomputed per bin in the
-//     context), 64 per ballot, written as 8 words.
-// The whole-level blurred pyramid never touches HBM.
+// of its keypoint in LDS with 32-bit loads (coordinates clamped to the
+// level, which makes the clamp-to-edge smoothing exact), then:
+//  * intensity centroid over the disc u^2 + v^2 <= 225 of the unsmoothed
+//    level, one lane per disc row: S_v = sum_u I and T_v = sum_u (u+16) I as
+//    dot products of 4 bytes against constant weight words (v_dot4_u32_u8);
+//    m10 = sum_v (T_v - 16 S_v), m01 = sum_v v S_v, reduced across the wave;
+//  * orientation bin: 30 lanes compare m with the Q14 bin boundaries at
+//    6 + 12 j degrees by exact integer half-plane / cross-product tests,
+//    a ballot counts them (bin = count mod 30, 0 for m = 0);
+//  * smoothing only of the 31 x 31 patch the tests can touch, separable
+//    7-tap [18 33 49 56 49 33 18] / 256 with each pass rounded half up;
+//    every output is two dot4 ops over an alignbyte window; the horizontal
+//    pass writes its result transposed so the vertical pass is again a
+//    contiguous dot product, and the final patch is stored transposed;
+//  * 256 tests on the bin-rotated pattern (precomputed per bin in the
+//    context), 64 per ballot, written as 8 words.
+// The whole-level smoothed pyramid never touches HBM.
+#include <string.h>
+
 #include "vsfe_internal.h"
 
 namespace vsfe {
 
-constexpr int ORB_R = 37, ORB_P = 31;
 constexpr int ORB_WAVES = 4;
+constexpr int R_STRIDE = 40;      // staged 37 x 37 neighbourhood, one row per 40 bytes
+constexpr int HT_STRIDE = 40;     // horizontal pass, transposed: [column][row], 37 rows used
+constexpr int B_STRIDE = 32;      // final smoothed patch, transposed: [column][row], 31 used
+constexpr uint32_t W_LO = 18u | (33u << 8) | (49u << 16) | (56u << 24);
+constexpr uint32_t W_HI = 49u | (33u << 8) | (18u << 16);
 
 struct OrbArgs {
     OrbTables tab;
-    int n_max, n_images, blur;
+    int n_max, n_images, blur, aligned0;
 };
 
+// Per disc row v = -15..15: byte u' (u = u' - 15) of 8 words; ones: 1 inside
+// the disc, ramp: (u + 16) inside the disc, 0 elsewhere (and at u' = 31).
+struct DiscTables {
+    uint32_t ones[31][8];
+    uint32_t ramp[31][8];
+};
+__constant__ DiscTables c_disc;
+
 __device__ __forceinline__ int half_plane(int64_t x, int64_t y) { return (y < 0 || (y == 0 && x < 0)) ? 1 : 0; }
+
+__device__ __forceinline__ uint32_t fetch4c(const uint8_t *row, int x, int w, bool aligned) {
+    if (aligned && x >= 0 && x + 3 < w) return *(const uint32_t *)(row + x);
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) v |= (uint32_t)row[min(max(x + j, 0), w - 1)] << (8 * j);
+    return v;
+}
 
 __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ imgs, const uint8_t *__restrict__ images,
                                                   const uint8_t *__restrict__ pyr, vsfe_kp_soa kps,
                                                   const int32_t *__restrict__ kp_count,
                                                   const int8_t *__restrict__ pat_rot, uint32_t *__restrict__ desc,
                                                   OrbArgs a) {
-    __shared__ uint8_t s_raw[ORB_WAVES][ORB_R * ORB_R + 7];
-    __shared__ uint8_t s_h[ORB_WAVES][ORB_R * ORB_P + 5];
-    __shared__ uint8_t s_b[ORB_WAVES][ORB_P * ORB_P + 3];
+    __shared__ __attribute__((aligned(16))) uint32_t s_r[ORB_WAVES][37 * R_STRIDE / 4 + 1];
+    __shared__ __attribute__((aligned(16))) uint32_t s_ht[ORB_WAVES][31 * HT_STRIDE / 4 + 1];
+    __shared__ __attribute__((aligned(16))) uint32_t s_b[ORB_WAVES][31 * B_STRIDE / 4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t slot = (int64_t)blockIdx.x * ORB_WAVES + wave;
     const int image = (int)(slot / a.n_max);
     const int i = (int)(slot - (int64_t)image * a.n_max);
     const bool active = image < a.n_images && i < kp_count[image];
+    uint8_t *R = (uint8_t *)s_r[wave];
+    uint8_t *HT = (uint8_t *)s_ht[wave];
+    uint8_t *BT = (uint8_t *)s_b[wave];
 
-    int x = 0, y = 0, lvl = 0;
-    LevelDev lv{};
+    int delta = 0;
     if (active) {
-        x = kps.x[slot];
-        y = kps.y[slot];
-        lvl = kps.level[slot];
-        lv = imgs[image].lv[lvl];
+        const int x = kps.x[slot], y = kps.y[slot], lvl = kps.level[slot];
+        const LevelDev lv = imgs[image].lv[lvl];
         const uint8_t *src = (lvl == 0 ? images : pyr) + lv.offset;
-        for (int q = lane; q < ORB_R * ORB_R; q += 64) {
-            const int r = q / ORB_R, cc = q - r * ORB_R;
-            const int gy = min(max(y - 18 + r, 0), lv.h - 1);
-            const int gx = min(max(x - 18 + cc, 0), lv.w - 1);
-            s_raw[wave][q] = src[(int64_t)gy * lv.pitch + gx];
+        const bool aligned = lvl > 0 || a.aligned0;
+        const int xs = (x - 18) & ~3;
+        delta = (x - 18) - xs;
+        uint32_t v[6];
+#pragma unroll
+        for (int u = 0; u < 6; u++) {
+            const int t = lane + 64 * u;
+            if (t < 37 * 10) {
+                const int r = t / 10, m = t - r * 10;
+                const int gy = min(max(y - 18 + r, 0), lv.h - 1);
+                v[u] = fetch4c(src + (int64_t)gy * lv.pitch, xs + 4 * m, lv.w, aligned);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 6; u++) {
+            const int t = lane + 64 * u;
+            if (t < 37 * 10) s_r[wave][(t / 10) * (R_STRIDE / 4) + t % 10] = v[u];
         }
     }
     __syncthreads();
+    // intensity centroid: lane v' = v + 15 < 31 sums its disc row
     int m10 = 0, m01 = 0;
-    if (active) {
-        for (int q = lane; q < ORB_P * ORB_P; q += 64) {
-            const int v = q / ORB_P - 15, u = q % ORB_P - 15;
-            if (u * u + v * v <= 225) {
-                const int I = s_raw[wave][(18 + v) * ORB_R + 18 + u];
-                m10 += u * I;
-                m01 += v * I;
-            }
+    if (active && lane < 31) {
+        const int al = (delta + 3) & 3;
+        const uint32_t *w = (const uint32_t *)(R + (lane + 3) * R_STRIDE + ((delta + 3) & ~3));
+        uint32_t S = 0, T = 0;
+        uint32_t prev = w[0];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const uint32_t nxt = w[k + 1];
+            const uint32_t b4 = __builtin_amdgcn_alignbyte(nxt, prev, al);
+            S = __builtin_amdgcn_udot4(b4, c_disc.ones[lane][k], S, false);
+            T = __builtin_amdgcn_udot4(b4, c_disc.ramp[lane][k], T, false);
+            prev = nxt;
         }
-        if (a.blur) {
-            for (int q = lane; q < ORB_R * ORB_P; q += 64) {
-                const int r = q / ORB_P, cc = q - r * ORB_P;
-                const uint8_t *p = &s_raw[wave][r * ORB_R + cc];
-                const int s = 18 * (p[0] + p[6]) + 33 * (p[1] + p[5]) + 49 * (p[2] + p[4]) + 56 * p[3];
-                s_h[wave][q] = (uint8_t)((s + 128) >> 8);
+        m10 = (int)T - 16 * (int)S;
+        m01 = (lane - 15) * (int)S;
+    }
+    if (active && a.blur) {
+        // horizontal pass: task (row r, group j) -> outputs at columns 4j..4j+3
+        for (int t = lane; t < 37 * 8; t += 64) {
+            const int r = t >> 3, j = t & 7;
+            const uint32_t *w = (const uint32_t *)(R + r * R_STRIDE + 4 * j);
+            const uint32_t d0 = w[0], d1 = w[1], d2 = w[2], d3 = w[3];
+            const uint32_t W0 = __builtin_amdgcn_alignbyte(d1, d0, delta);
+            const uint32_t W1 = __builtin_amdgcn_alignbyte(d2, d1, delta);
+            const uint32_t W2 = __builtin_amdgcn_alignbyte(d3, d2, delta);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int c = 4 * j + k;
+                if (c >= 31) break;
+                const uint32_t lo = __builtin_amdgcn_alignbyte(W1, W0, k);
+                const uint32_t hi = __builtin_amdgcn_alignbyte(W2, W1, k);
+                const uint32_t s = __builtin_amdgcn_udot4(lo, W_LO, __builtin_amdgcn_udot4(hi, W_HI, 128u, false), false);
+                HT[c * HT_STRIDE + r] = (uint8_t)(s >> 8);
             }
         }
     }
@@ -84,15 +142,26 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
     }
     __syncthreads();
     if (active) {
-        for (int q = lane; q < ORB_P * ORB_P; q += 64) {
-            const int r = q / ORB_P, cc = q - r * ORB_P;
-            if (a.blur) {
-                const uint8_t *p = &s_h[wave][r * ORB_P + cc];
-                const int s = 18 * (p[0] + p[6 * ORB_P]) + 33 * (p[ORB_P] + p[5 * ORB_P]) +
-                              49 * (p[2 * ORB_P] + p[4 * ORB_P]) + 56 * p[3 * ORB_P];
-                s_b[wave][q] = (uint8_t)((s + 128) >> 8);
-            } else {
-                s_b[wave][q] = s_raw[wave][(r + 3) * ORB_R + cc + 3];
+        if (a.blur) {
+            // vertical pass on the transposed rows: task (column c, group j) -> rows 4j..4j+3
+            for (int t = lane; t < 31 * 8; t += 64) {
+                const int c = t >> 3, j = t & 7;
+                const uint32_t *w = (const uint32_t *)(HT + c * HT_STRIDE + 4 * j);
+                const uint32_t W0 = w[0], W1 = w[1], W2 = w[2];
+                uint32_t word = 0;
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t lo = __builtin_amdgcn_alignbyte(W1, W0, k);
+                    const uint32_t hi = __builtin_amdgcn_alignbyte(W2, W1, k);
+                    const uint32_t s = __builtin_amdgcn_udot4(lo, W_LO, __builtin_amdgcn_udot4(hi, W_HI, 128u, false), false);
+                    word |= (s >> 8) << (8 * k);
+                }
+                s_b[wave][(c * B_STRIDE + 4 * j) >> 2] = word;
+            }
+        } else {
+            for (int t = lane; t < 31 * 31; t += 64) {
+                const int c = t / 31, r = t - c * 31;
+                BT[c * B_STRIDE + r] = R[(r + 3) * R_STRIDE + delta + c + 3];
             }
         }
     }
@@ -104,7 +173,7 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         ge = hm != hb ? hm > hb : (bx * (int64_t)m01 - by * (int64_t)m10 >= 0);
     }
     const uint64_t gem = __ballot(ge);
-    int bin = (m10 == 0 && m01 == 0) ? 0 : (__popcll(gem) % 30);
+    const int bin = (m10 == 0 && m01 == 0) ? 0 : (__popcll(gem) % 30);
     __syncthreads();
     if (active) {
         const int8_t *pr = pat_rot + (int64_t)bin * 256 * 4;
@@ -113,8 +182,8 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         for (int rnd = 0; rnd < 4; rnd++) {
             const int t = rnd * 64 + lane;
             const char4 q = *(const char4 *)(pr + 4 * t);
-            const int va = s_b[wave][(15 + q.y) * ORB_P + 15 + q.x];
-            const int vb = s_b[wave][(15 + q.w) * ORB_P + 15 + q.z];
+            const int va = BT[(15 + q.x) * B_STRIDE + 15 + q.y];
+            const int vb = BT[(15 + q.z) * B_STRIDE + 15 + q.w];
             const uint64_t bits = __ballot(va < vb);
             words[2 * rnd] = (uint32_t)bits;
             words[2 * rnd + 1] = (uint32_t)(bits >> 32);
@@ -129,6 +198,30 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         if (lane == 0) kps.bin[slot] = (uint8_t)bin;
     }
 }
+
+static bool g_disc_ready[64];
+
+static int32_t upload_disc(int device, hipStream_t st) {
+    if (device >= 0 && device < 64 && g_disc_ready[device]) return VSFE_OK;
+    DiscTables t;
+    memset(&t, 0, sizeof(t));
+    for (int vi = 0; vi < 31; vi++) {
+        const int v = vi - 15;
+        for (int ui = 0; ui < 31; ui++) {
+            const int u = ui - 15;
+            if (u * u + v * v > 225) continue;
+            t.ones[vi][ui >> 2] |= 1u << (8 * (ui & 3));
+            t.ramp[vi][ui >> 2] |= (uint32_t)(u + 16) << (8 * (ui & 3));
+        }
+    }
+    (void)st;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_disc), &t, sizeof(t), 0, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(VSFE_EHIP, "upload of the disc tables failed");
+    if (device >= 0 && device < 64) g_disc_ready[device] = true;
+    return VSFE_OK;
+}
+
+int32_t orb_prepare(int device) { return upload_disc(device, nullptr); }
 
 }  // namespace vsfe
 
@@ -147,6 +240,7 @@ extern "C" int32_t orb_describe(const vsfe_ctx *ctx, const vsfe_batch *b, const 
     a.n_max = ctx->p.n_max;
     a.n_images = b->n_images;
     a.blur = ctx->p.blur;
+    a.aligned0 = b->aligned_input && (((uintptr_t)images & 3) == 0) ? 1 : 0;
     const int64_t slots = b->info.kp_capacity;
     const int64_t blocks = (slots + ORB_WAVES - 1) / ORB_WAVES;
     if (blocks <= 0) return VSFE_OK;

@@ -14,12 +14,14 @@ namespace vsfe {
 // Per-level geometry as the kernels see it (one 64-byte record).
 struct LevelDev {
     int32_t w, h, pitch, cell;
-    int32_t ncx, ncy, scale_q16, pad;
+    int32_t ncx, ncy, scale_q16;
+    int32_t xtab, ytab;    // first entries of the resampling tables (levels >= 1)
+    int32_t pad;
     int64_t offset;        // level 0: into the input buffer, else into the pyramid buffer
     int64_t cell_offset;   // global index of the first cell of this level
     int64_t crf_offset;    // first element of this level in the response dump
 };
-static_assert(sizeof(LevelDev) == 56, "LevelDev layout");
+static_assert(sizeof(LevelDev) == 64, "LevelDev layout");
 
 struct ImageDev {
     int32_t w, h, n_levels, pad;
@@ -30,11 +32,16 @@ struct ImageDev {
     LevelDev lv[VSFE_MAX_LEVELS];
 };
 
-// Output tile of the pyramid kernel: PYR_TW x PYR_TH pixels of one level.
-constexpr int PYR_TW = 64;
-constexpr int PYR_TH = 16;
+// Output tile of the pyramid kernel: PYR_TW x PYR_TH pixels of one level,
+// resampled from a staged source window of at most PYR_SH x PYR_SW bytes
+// starting at (xs, ys) of the level above (xs and ncols are multiples of 16).
+constexpr int PYR_TW = 128;
+constexpr int PYR_TH = 32;
+constexpr int PYR_SW = 256;
+constexpr int PYR_SH = 44;
 struct PyrItem {
     uint16_t image, tx, ty, pad;
+    uint16_t xs, ys, ncols, nrows;
 };
 
 // Detector work item: a rectangle of whole cells of one level.
@@ -76,6 +83,11 @@ struct vsfe_batch {
     std::vector<int32_t> pyr_start;
     std::vector<vsfe::PyrItem> h_pyr_items;
     vsfe::PyrItem *d_pyr_items = nullptr;
+    // resampling tables: entry = source index | (weight << 16), weight 0 at the far edge
+    std::vector<uint32_t> h_coord;
+    uint32_t *d_coord = nullptr;
+    bool aligned_input = true;                   // level-0 rows start on 4-byte boundaries
+    bool aligned_input16 = true;                 // ... and on 16-byte boundaries
     int32_t n_det_items = 0;
     std::vector<vsfe::DetItem> h_det_items;
     vsfe::DetItem *d_det_items = nullptr;
@@ -91,6 +103,9 @@ void set_error(const std::string &msg);
 int32_t fail(int32_t code, const std::string &msg);
 int32_t check_launch(const char *what);
 int32_t check_common(const vsfe_ctx *ctx, const vsfe_batch *b, int32_t *status);
+
+// one-time upload of the orientation disc tables to the current device
+int32_t orb_prepare(int device);
 
 // level geometry shared by the host planner
 void level_size(int32_t W, int32_t H, int32_t l, int32_t *Wl, int32_t *Hl);

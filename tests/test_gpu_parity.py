@@ -110,7 +110,7 @@ def test_parameter_variants(fe_mod, pattern, variant):
     run_and_compare(fe_mod, [l, r], p, pattern)
 
 
-@pytest.mark.parametrize("tile", [(8, 8), (32, 16), (128, 64), (96, 40)])
+@pytest.mark.parametrize("tile", [(8, 8), (32, 16), (128, 32), (96, 24), (64, 32)])
 def test_tile_shapes_identical(fe_mod, pattern, tile):
     l, r = scenes.stereo_pair(78, 333, 201, 80, 40)
     run_and_compare(fe_mod, [l, r], Params(), pattern, tile=tile)
