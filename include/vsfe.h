@@ -223,6 +223,59 @@ int32_t stereo_match(const vsfe_ctx *ctx, const vsfe_batch *b, const vsfe_kp_soa
                      const int32_t *kp_count, const uint32_t *desc, int32_t *match_idx,
                      uint16_t *match_dist, int16_t *match_disp, int32_t *status, void *stream);
 
+/* ---------------------------------------------------- learned cell proposer
+ *
+ * Not part of the paper: a small CNN on pyramid level 3 predicts which
+ * native-scale cells will hold final keypoints; fast_br_detect's cell_mask
+ * then skips the others.  Network: x = (I_3 - 128) / 128, three 3x3
+ * stride-2 convolutions with zero padding 1 (1 -> 16 -> 32 -> 32 channels,
+ * ReLU) and a 1x1 head (32 -> 1), one logit per stride-8 grid position.
+ * Parameters: one vector of 14081 values, OIHW weights then biases per
+ * layer (w1 b1 w2 b2 w3 b3 w4 b4); the kernels read a bfloat16 copy and
+ * keep bfloat16 activations with float32 sums.  Grid logits are float32,
+ * images' grids back to back in image order, row-major.  All calls need
+ * n_levels >= 4 (EINVAL otherwise) and a workspace of workspace_bytes. */
+typedef struct vsfe_cnn_info {
+    int64_t workspace_bytes;  /* activations, gradients, partial sums        */
+    int64_t grid_elems;       /* grid logits of all images                   */
+    int64_t n_cells0;         /* native-scale cells (cell_mask size)         */
+    int32_t n_params;         /* 14081                                       */
+} vsfe_cnn_info;
+
+int32_t vsfe_cnn_info_get(const vsfe_batch *b, vsfe_cnn_info *out);
+
+/* Forward pass on level 3 of every image (pyr = pyramid buffer after
+ * pyramid_build); writes grid_logits and keeps activations in the
+ * workspace for cnn_backward. */
+int32_t cnn_forward(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *pyr,
+                    const uint16_t *params_bf16, void *workspace, float *grid_logits,
+                    int32_t *status, void *stream);
+
+/* Forward pass, then per native-scale cell the maximum logit of the grid
+ * positions whose projected centre ((8 j + 4) S_3 + 2^15) >> 16 lies in the
+ * cell (+inf if none).  cell_mask[c] = logit >= thresh (cells without a
+ * position are kept).  cell_logits is nullable. */
+int32_t cnn_propose(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *pyr,
+                    const uint16_t *params_bf16, float thresh, void *workspace,
+                    float *grid_logits, float *cell_logits, uint8_t *cell_mask,
+                    int32_t *status, void *stream);
+
+/* Gradient of the mean binary cross-entropy over all grid positions,
+ * positives weighted by pos_weight (> 0), w.r.t. the parameters; needs the
+ * workspace of a cnn_forward with the same parameters and inputs.  grad:
+ * 14081 float32 (overwritten); loss: one float32 (nullable).
+ * Deterministic (fixed-order reductions). */
+int32_t cnn_backward(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *pyr,
+                     const uint16_t *params_bf16, void *workspace, const float *grid_logits,
+                     const float *grid_targets, float pos_weight, float *grad, float *loss,
+                     int32_t *status, void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on n float32 parameters; also
+ * refreshes their bfloat16 copy (round to nearest even). */
+int32_t cnn_adam_step(float *params, uint16_t *params_bf16, float *m, float *v,
+                      const float *grad, int32_t n, float lr, float beta1, float beta2,
+                      float eps, int32_t step, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

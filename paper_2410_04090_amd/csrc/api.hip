@@ -392,6 +392,7 @@ int32_t vsfe_batch_destroy(vsfe_batch *b) {
     if (b->d_coord) (void)hipFree(b->d_coord);
     if (b->d_det_items) (void)hipFree(b->d_det_items);
     if (b->d_chunks) (void)hipFree(b->d_chunks);
+    cnn_release(b);
     delete b;
     return VSFE_OK;
 }
@@ -421,6 +422,7 @@ int32_t vsfe_batch_create(const vsfe_ctx *ctx, int32_t n, const int32_t *widths,
     if (!rc) rc = upload(b->h_coord, &b->d_coord);
     if (!rc) rc = upload(b->h_det_items, &b->d_det_items);
     if (!rc) rc = upload(b->h_chunks, &b->d_chunks);
+    if (!rc) rc = cnn_setup(b);
     if (rc) {
         vsfe_batch_destroy(b);
         return rc;

@@ -1,0 +1,645 @@
+// Learned cell proposer: a small CNN on pyramid level 3 that predicts which
+// native-scale cells will hold final keypoints, so the exact detector runs
+// only there (the gating itself is in fast_br_detect).
+//
+// Network (one logit per stride-8 position of level 3):
+//   x = (I_3 - 128) / 128 -> conv3x3 s2 (1 -> 16) -> ReLU -> conv3x3 s2
+//   (16 -> 32) -> ReLU -> conv3x3 s2 (32 -> 32) -> ReLU -> conv1x1 (32 -> 1).
+// Padding 1, ceil(in / 2) outputs per axis.  Parameters are one flat
+// vector, OIHW weights followed by biases per layer.  Weights and stored
+// activations are bfloat16 (NHWC), sums are float32.
+//
+//  * conv1 (K = 9) runs on the VALU, one thread per output pixel;
+//  * conv2 (K = 144) and conv3 (K = 288) are implicit GEMMs on
+//    v_mfma_f32_16x16x32_bf16: one wave computes 16 output pixels x 32
+//    channels, each lane feeding 8 consecutive channels of one tap as its
+//    K slice (weights repacked to [co][tap][ci]); the 1x1 head is fused in
+//    conv3's epilogue with a 16-lane shuffle reduction;
+//  * cell logits: per native-scale cell, the maximum over the grid
+//    positions whose projected centre ((8 j + 4) S_3 + 2^15) >> 16 falls in
+//    it (a cell with none is always kept);
+//  * training: mean binary cross-entropy with a positive-class weight,
+//    backward in float32 on the VALU, weight gradients as per-block partial
+//    sums reduced in a fixed order (deterministic), then Adam.
+#include <string.h>
+
+#include <algorithm>
+
+#include "vsfe_internal.h"
+
+namespace vsfe {
+
+constexpr int CNN_NPARAM = 14081;
+constexpr int P_W1 = 0, P_B1 = 144, P_W2 = 160, P_B2 = 4768, P_W3 = 4800, P_B3 = 14016, P_W4 = 14048, P_B4 = 14080;
+constexpr int CNN_PARTS = 256;            // partial-sum blocks of the weight gradients
+
+struct CnnImg {
+    int32_t w0, h0, w3, h3, w1, h1, w2, h2, w4, h4, ncx0, ncy0, cell0, pitch3;
+    int64_t lvl3;                      // byte offset of level 3 in the pyramid buffer
+    int64_t px1, px2, px4;             // first pixel of this image in each layer's arrays
+    int64_t c0;                        // first native-scale cell
+};
+
+struct CnnPlan {
+    int n = 0;
+    std::vector<CnnImg> h_img;
+    CnnImg *d_img = nullptr;
+    std::vector<int32_t> h_pre;        // prefixes (n + 1 each): px1, px2, px4, tiles2, tiles4, cells
+    int32_t *d_pre = nullptr;
+    int64_t px1 = 0, px2 = 0, px4 = 0, t2 = 0, t4 = 0, cells = 0;
+    int64_t off_wp2 = 0, off_wp3 = 0, off_a1 = 0, off_a2 = 0, off_a3 = 0, off_g1 = 0, off_g2 = 0, off_g3 = 0,
+            off_dz = 0, off_lz = 0, off_part = 0, total = 0;
+};
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf(uint16_t v) { return __builtin_bit_cast(float, (uint32_t)v << 16); }
+__device__ __forceinline__ uint16_t to_bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// largest i with pre[i] <= g (pre is nondecreasing, pre[0] = 0)
+__device__ __forceinline__ int find_image(const int32_t *pre, int n, int64_t g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// --------------------------------------------------------------- forward
+// Repack conv2 / conv3 weights from OIHW to [co][tap][ci] (bf16).
+__global__ void cnn_pack_kernel(const uint16_t *__restrict__ prm, uint16_t *__restrict__ wp2, uint16_t *__restrict__ wp3) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 32 * 9 * 16) {
+        const int co = i / (9 * 16), t = (i / 16) % 9, ci = i % 16;
+        wp2[i] = prm[P_W2 + (co * 16 + ci) * 9 + t];
+    }
+    if (i < 32 * 9 * 32) {
+        const int co = i / (9 * 32), t = (i / 32) % 9, ci = i % 32;
+        wp3[i] = prm[P_W3 + (co * 32 + ci) * 9 + t];
+    }
+}
+
+__global__ __launch_bounds__(256) void cnn_conv1_kernel(const CnnImg *__restrict__ imgs, const int32_t *__restrict__ pre,
+                                                        int n, int64_t total, const uint8_t *__restrict__ pyr,
+                                                        const uint16_t *__restrict__ prm, uint16_t *__restrict__ a1) {
+    __shared__ float s_w[160];
+    if (threadIdx.x < 160) s_w[threadIdx.x] = bf(prm[threadIdx.x]);
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_image(pre, n, g);
+    const CnnImg im = imgs[i];
+    const int p = (int)(g - im.px1);
+    const int oy = p / im.w1, ox = p - oy * im.w1;
+    float x[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const int iy = 2 * oy + k / 3 - 1, ix = 2 * ox + k % 3 - 1;
+        x[k] = (iy >= 0 && iy < im.h3 && ix >= 0 && ix < im.w3)
+                   ? ((float)pyr[im.lvl3 + (int64_t)iy * im.pitch3 + ix] - 128.0f) * (1.0f / 128.0f)
+                   : 0.0f;
+    }
+    uint32_t packed[8];
+#pragma unroll
+    for (int co = 0; co < 16; co += 2) {
+        float s0 = s_w[P_B1 + co], s1 = s_w[P_B1 + co + 1];
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            s0 += s_w[co * 9 + k] * x[k];
+            s1 += s_w[(co + 1) * 9 + k] * x[k];
+        }
+        packed[co / 2] = (uint32_t)to_bf(fmaxf(s0, 0.0f)) | ((uint32_t)to_bf(fmaxf(s1, 0.0f)) << 16);
+    }
+    uint4 *dst = (uint4 *)(a1 + (int64_t)g * 16);
+    dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+    dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+}
+
+// Implicit-GEMM 3x3 stride-2 convolution CIN -> 32 on MFMA; with HEAD the
+// 1x1 head is applied to the (bf16-rounded) outputs and z is written.
+template <int CIN, bool HEAD>
+__global__ __launch_bounds__(256) void cnn_conv_mfma_kernel(const CnnImg *__restrict__ imgs,
+                                                            const int32_t *__restrict__ pre_tiles, int n,
+                                                            int64_t total_tiles, const uint16_t *__restrict__ ain,
+                                                            uint16_t *__restrict__ aout, const uint16_t *__restrict__ wp,
+                                                            const uint16_t *__restrict__ prm, float *__restrict__ z) {
+    constexpr int NCH = CIN == 16 ? 5 : 9;     // K chunks of 32 (conv2: pairs of taps, the last padded)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    if (tile >= total_tiles) return;
+    const int i = find_image(pre_tiles, n, tile);
+    const CnnImg im = imgs[i];
+    const int in_w = CIN == 16 ? im.w1 : im.w2, in_h = CIN == 16 ? im.h1 : im.h2;
+    const int out_w = CIN == 16 ? im.w2 : im.w4, out_h = CIN == 16 ? im.h2 : im.h4;
+    const int64_t in_base = CIN == 16 ? im.px1 : im.px2, out_base = CIN == 16 ? im.px2 : im.px4;
+    const int npx = out_w * out_h;
+    const int p0 = (int)(tile - pre_tiles[i]) * 16;
+    const int m = lane & 15, grp = lane >> 4;
+    const int pm = p0 + m;
+    const bool valid = pm < npx;
+    const int oy = valid ? pm / out_w : 0, ox = valid ? pm - oy * out_w : 0;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NCH; c++) {
+        const int t = CIN == 16 ? 2 * c + (grp >> 1) : c;
+        const int ci0 = CIN == 16 ? 8 * (grp & 1) : 8 * grp;
+        uint4 av = make_uint4(0, 0, 0, 0), b0 = make_uint4(0, 0, 0, 0), b1 = make_uint4(0, 0, 0, 0);
+        if (t < 9) {
+            const int iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
+            if (valid && iy >= 0 && iy < in_h && ix >= 0 && ix < in_w)
+                av = *(const uint4 *)(ain + ((in_base + (int64_t)iy * in_w + ix) * CIN + ci0));
+            b0 = *(const uint4 *)(wp + ((m * 9 + t) * CIN + ci0));
+            b1 = *(const uint4 *)(wp + (((m + 16) * 9 + t) * CIN + ci0));
+        }
+        const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
+    }
+    // lane holds output channels m and m + 16 of pixels p0 + 4 grp + r
+    const int bias_at = CIN == 16 ? P_B2 : P_B3;
+    const float bb0 = bf(prm[bias_at + m]), bb1 = bf(prm[bias_at + m + 16]);
+    float hw0 = 0.f, hw1 = 0.f;
+    if (HEAD) {
+        hw0 = bf(prm[P_W4 + m]);
+        hw1 = bf(prm[P_W4 + m + 16]);
+    }
+    float part[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int p = p0 + 4 * grp + r;
+        const uint16_t v0 = to_bf(fmaxf(acc0[r] + bb0, 0.0f)), v1 = to_bf(fmaxf(acc1[r] + bb1, 0.0f));
+        if (p < npx) {
+            aout[(out_base + p) * 32 + m] = v0;
+            aout[(out_base + p) * 32 + m + 16] = v1;
+        }
+        part[r] = hw0 * bf(v0) + hw1 * bf(v1);
+    }
+    if (HEAD) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) part[r] += __shfl_xor(part[r], o);
+        }
+        if (m == 0) {
+            const float b4 = bf(prm[P_B4]);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int p = p0 + 4 * grp + r;
+                if (p < npx) z[out_base + p] = part[r] + b4;
+            }
+        }
+    }
+}
+
+__global__ void cnn_cells_kernel(const CnnImg *__restrict__ imgs, const int32_t *__restrict__ pre_cells, int n,
+                                 int64_t total, const float *__restrict__ z, float thresh,
+                                 float *__restrict__ cell_logit, uint8_t *__restrict__ mask, int S3) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_image(pre_cells, n, g);
+    const CnnImg im = imgs[i];
+    const int c = (int)(g - im.c0);
+    const int cy = c / im.ncx0, cx = c - cy * im.ncx0;
+    auto proj = [&](int j, int lim) { return min((int)(((int64_t)(8 * j + 4) * S3 + 32768) >> 16), lim - 1); };
+    // first grid column / row whose projected centre reaches the cell
+    int j0 = max(0, (int)(((int64_t)cx * im.cell0 * 65536 / S3 - 4) / 8) - 2);
+    while (j0 < im.w4 && proj(j0, im.w0) < cx * im.cell0) j0++;
+    int i0 = max(0, (int)(((int64_t)cy * im.cell0 * 65536 / S3 - 4) / 8) - 2);
+    while (i0 < im.h4 && proj(i0, im.h0) < cy * im.cell0) i0++;
+    float best = -INFINITY;
+    bool any = false;
+    for (int a = i0; a < im.h4 && proj(a, im.h0) < (cy + 1) * im.cell0; a++)
+        for (int b = j0; b < im.w4 && proj(b, im.w0) < (cx + 1) * im.cell0; b++) {
+            best = fmaxf(best, z[im.px4 + (int64_t)a * im.w4 + b]);
+            any = true;
+        }
+    if (!any) best = INFINITY;
+    if (cell_logit) cell_logit[g] = best;
+    if (mask) mask[g] = (uint8_t)(best >= thresh ? 1 : 0);
+}
+
+// --------------------------------------------------------------- backward
+// dz = d(mean BCE)/dz, per-position loss, and the conv3 output gradient
+// g3 = dz w4 [a3 > 0].
+__global__ void cnn_head_bwd_kernel(int64_t total, const float *__restrict__ z, const float *__restrict__ target,
+                                    float pos_weight, const uint16_t *__restrict__ prm,
+                                    const uint16_t *__restrict__ a3, float *__restrict__ dz, float *__restrict__ lz,
+                                    float *__restrict__ g3) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= total) return;
+    const float zz = z[p], t = target[p];
+    const float inv_n = 1.0f / (float)total;
+    const float sp_pos = fmaxf(-zz, 0.f) + log1pf(expf(-fabsf(zz)));   // -log sigmoid(z)
+    const float sp_neg = fmaxf(zz, 0.f) + log1pf(expf(-fabsf(zz)));    // -log(1 - sigmoid(z))
+    const float s = 1.0f / (1.0f + expf(-zz));
+    lz[p] = (pos_weight * t * sp_pos + (1.f - t) * sp_neg) * inv_n;
+    const float d = (pos_weight * t * (s - 1.f) + (1.f - t) * s) * inv_n;
+    dz[p] = d;
+    for (int co = 0; co < 32; co++) {
+        const float a = bf(a3[p * 32 + co]);
+        g3[p * 32 + co] = a > 0.f ? d * bf(prm[P_W4 + co]) : 0.f;
+    }
+}
+
+// Partial sums of the head gradients over a pixel range.
+__global__ __launch_bounds__(256) void cnn_head_wgrad_kernel(int64_t total, const float *__restrict__ dz,
+                                                             const uint16_t *__restrict__ a3,
+                                                             float *__restrict__ part) {
+    __shared__ float s_acc[256][33];
+    const int64_t chunk = (total + CNN_PARTS - 1) / CNN_PARTS;
+    const int64_t lo = blockIdx.x * chunk, hi = min(total, lo + chunk);
+    float acc[33];
+    for (int k = 0; k < 33; k++) acc[k] = 0.f;
+    for (int64_t p = lo + threadIdx.x; p < hi; p += 256) {
+        const float d = dz[p];
+        for (int co = 0; co < 32; co++) acc[co] += d * bf(a3[p * 32 + co]);
+        acc[32] += d;
+    }
+    for (int k = 0; k < 33; k++) s_acc[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < 33) {
+        float s = 0.f;
+        for (int t = 0; t < 256; t++) s += s_acc[t][threadIdx.x];
+        part[(int64_t)blockIdx.x * CNN_NPARAM + (threadIdx.x < 32 ? P_W4 + threadIdx.x : P_B4)] = s;
+    }
+}
+
+// Partial sums of a 3x3 stride-2 convolution's weight / bias gradients:
+// dW[co][ci][t] = sum_p g[p][co] a[in(p, t)][ci].  U8IN: the input is the
+// level-3 image, x = (I - 128) / 128.
+template <int CIN, int COUT, bool U8IN>
+__global__ __launch_bounds__(256) void cnn_wgrad_kernel(const CnnImg *__restrict__ imgs, const int32_t *__restrict__ pre_out,
+                                                        int n, int64_t total, const float *__restrict__ g,
+                                                        const uint16_t *__restrict__ ain, const uint8_t *__restrict__ pyr,
+                                                        float *__restrict__ part, int w_at, int b_at) {
+    constexpr int NW = COUT * 9 * CIN;
+    constexpr int PER = NW < 256 * 9 ? (NW + 255) / 256 : 9;   // weights per thread (grid.y splits the rest)
+    constexpr int PB = 16;                       // pixels staged per round
+    const int wbase = blockIdx.y * 256 * PER;
+    __shared__ float s_g[PB][COUT];
+    __shared__ float s_a[PB][9 * CIN];
+    const int64_t chunk = (total + CNN_PARTS - 1) / CNN_PARTS;
+    const int64_t lo = blockIdx.x * chunk, hi = min(total, lo + chunk);
+    float acc[PER], bacc = 0.f;
+#pragma unroll
+    for (int k = 0; k < PER; k++) acc[k] = 0.f;
+    for (int64_t base = lo; base < hi; base += PB) {
+        // stage the output gradients and input patches of PB pixels
+        for (int q = threadIdx.x; q < PB * COUT; q += 256) {
+            const int pp = q / COUT, co = q - pp * COUT;
+            const int64_t p = base + pp;
+            s_g[pp][co] = p < hi ? g[p * COUT + co] : 0.f;
+        }
+        for (int q = threadIdx.x; q < PB * 9 * CIN; q += 256) {
+            const int pp = q / (9 * CIN), r = q - pp * 9 * CIN, t = r / CIN, ci = r - t * CIN;
+            const int64_t p = base + pp;
+            float v = 0.f;
+            if (p < hi) {
+                const int i = find_image(pre_out, n, p);
+                const CnnImg im = imgs[i];
+                const int ow = CIN == 1 ? im.w1 : (CIN == 16 ? im.w2 : im.w4);
+                const int iw = CIN == 1 ? im.w3 : (CIN == 16 ? im.w1 : im.w2);
+                const int ih = CIN == 1 ? im.h3 : (CIN == 16 ? im.h1 : im.h2);
+                const int64_t ob = CIN == 1 ? im.px1 : (CIN == 16 ? im.px2 : im.px4);
+                const int64_t ib = CIN == 16 ? im.px1 : im.px2;
+                const int lp = (int)(p - ob), oy = lp / ow, ox = lp - oy * ow;
+                const int iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
+                if (iy >= 0 && iy < ih && ix >= 0 && ix < iw) {
+                    if (U8IN) v = ((float)pyr[im.lvl3 + (int64_t)iy * im.pitch3 + ix] - 128.0f) * (1.0f / 128.0f);
+                    else v = bf(ain[(ib + (int64_t)iy * iw + ix) * CIN + ci]);
+                }
+            }
+            s_a[pp][r] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const int w = wbase + threadIdx.x + 256 * k;
+            if (w < NW) {
+                const int co = w / (9 * CIN), r = w - co * 9 * CIN;
+                float s = acc[k];
+                for (int pp = 0; pp < PB; pp++) s += s_g[pp][co] * s_a[pp][r];
+                acc[k] = s;
+            }
+        }
+        if (blockIdx.y == 0 && threadIdx.x < COUT)
+            for (int pp = 0; pp < PB; pp++) bacc += s_g[pp][threadIdx.x];
+        __syncthreads();
+    }
+    float *out = part + (int64_t)blockIdx.x * CNN_NPARAM;
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const int w = wbase + threadIdx.x + 256 * k;
+        if (w < NW) {
+            const int co = w / (9 * CIN), r = w - co * 9 * CIN, t = r / CIN, ci = r - t * CIN;
+            out[w_at + (co * CIN + ci) * 9 + t] = acc[k];
+        }
+    }
+    if (blockIdx.y == 0 && threadIdx.x < COUT) out[b_at + threadIdx.x] = bacc;
+}
+
+// Input gradient of a 3x3 stride-2 convolution (transposed-convolution
+// gather), times the ReLU mask of the input activation.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void cnn_dgrad_kernel(const CnnImg *__restrict__ imgs, const int32_t *__restrict__ pre_in,
+                                                        int n, int64_t total_in, const float *__restrict__ gout,
+                                                        const uint16_t *__restrict__ ain, const uint16_t *__restrict__ prm,
+                                                        int w_at, float *__restrict__ gin) {
+    __shared__ float s_w[COUT * CIN * 9];
+    for (int q = threadIdx.x; q < COUT * CIN * 9; q += 256) s_w[q] = bf(prm[w_at + q]);
+    __syncthreads();
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total_in * CIN) return;
+    const int64_t q = e / CIN;
+    const int ci = (int)(e - q * CIN);
+    const int i = find_image(pre_in, n, q);
+    const CnnImg im = imgs[i];
+    const int iw = CIN == 16 ? im.w1 : im.w2, ow = CIN == 16 ? im.w2 : im.w4, oh = CIN == 16 ? im.h2 : im.h4;
+    const int64_t ib = CIN == 16 ? im.px1 : im.px2, ob = CIN == 16 ? im.px2 : im.px4;
+    const int lq = (int)(q - ib), iy = lq / iw, ix = lq - iy * iw;
+    float acc = 0.f;
+    if (bf(ain[q * CIN + ci]) > 0.f) {
+        for (int ky = 0; ky < 3; ky++) {
+            const int ty = iy + 1 - ky;
+            if (ty & 1) continue;
+            const int oy = ty >> 1;
+            if (oy < 0 || oy >= oh) continue;
+            for (int kx = 0; kx < 3; kx++) {
+                const int tx = ix + 1 - kx;
+                if (tx & 1) continue;
+                const int ox = tx >> 1;
+                if (ox < 0 || ox >= ow) continue;
+                const float *gp = gout + (ob + (int64_t)oy * ow + ox) * COUT;
+                const int t = ky * 3 + kx;
+                for (int co = 0; co < COUT; co++) acc += gp[co] * s_w[(co * CIN + ci) * 9 + t];
+            }
+        }
+    }
+    gin[e] = acc;
+}
+
+// grad[k] = sum of the partials (fixed order); loss = sum of lz.
+__global__ void cnn_reduce_kernel(const float *__restrict__ part, float *__restrict__ grad, const float *__restrict__ lz,
+                                  int64_t n_lz, float *__restrict__ loss) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < CNN_NPARAM) {
+        float s = 0.f;
+        for (int b = 0; b < CNN_PARTS; b++) s += part[(int64_t)b * CNN_NPARAM + k];
+        grad[k] = s;
+    }
+    if (blockIdx.x == 0 && loss) {
+        __shared__ float s_l[256];
+        float s = 0.f;
+        for (int64_t p = threadIdx.x; p < n_lz; p += blockDim.x) s += lz[p];
+        s_l[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.f;
+            for (int j = 0; j < (int)blockDim.x; j++) t += s_l[j];
+            loss[0] = t;
+        }
+    }
+}
+
+__global__ void cnn_adam_kernel(float *__restrict__ w, uint16_t *__restrict__ wb, float *__restrict__ m,
+                                float *__restrict__ v, const float *__restrict__ g, int n, float lr, float b1, float b2,
+                                float eps, float c1, float c2) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    const float wk = w[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+    w[k] = wk;
+    wb[k] = to_bf(wk);
+}
+
+// --------------------------------------------------------------- host side
+static int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+int32_t cnn_setup(vsfe_batch *b) {
+    if (b->info.n_levels < 4) return VSFE_OK;            // no level 3: the proposer is unavailable
+    CnnPlan *P = new CnnPlan();
+    const int n = b->n_images;
+    P->n = n;
+    P->h_img.resize(n);
+    std::vector<int32_t> pre1(n + 1), pre2(n + 1), pre4(n + 1), pt2(n + 1), pt4(n + 1), pc(n + 1);
+    int64_t s1 = 0, s2 = 0, s4 = 0, st2 = 0, st4 = 0, sc = 0;
+    for (int i = 0; i < n; i++) {
+        const ImageDev &im = b->images[i];
+        CnnImg &c = P->h_img[i];
+        c.w0 = im.w;
+        c.h0 = im.h;
+        c.w3 = im.lv[3].w;
+        c.h3 = im.lv[3].h;
+        c.w1 = (c.w3 + 1) / 2;
+        c.h1 = (c.h3 + 1) / 2;
+        c.w2 = (c.w1 + 1) / 2;
+        c.h2 = (c.h1 + 1) / 2;
+        c.w4 = (c.w2 + 1) / 2;
+        c.h4 = (c.h2 + 1) / 2;
+        c.ncx0 = im.lv[0].ncx;
+        c.ncy0 = im.lv[0].ncy;
+        c.cell0 = im.lv[0].cell;
+        c.pitch3 = im.lv[3].pitch;
+        c.lvl3 = im.lv[3].offset;
+        pre1[i] = (int32_t)s1;
+        pre2[i] = (int32_t)s2;
+        pre4[i] = (int32_t)s4;
+        pt2[i] = (int32_t)st2;
+        pt4[i] = (int32_t)st4;
+        pc[i] = (int32_t)sc;
+        c.px1 = s1;
+        c.px2 = s2;
+        c.px4 = s4;
+        c.c0 = im.cell0_offset;
+        s1 += (int64_t)c.w1 * c.h1;
+        s2 += (int64_t)c.w2 * c.h2;
+        s4 += (int64_t)c.w4 * c.h4;
+        st2 += ((int64_t)c.w2 * c.h2 + 15) / 16;
+        st4 += ((int64_t)c.w4 * c.h4 + 15) / 16;
+        sc += (int64_t)c.ncx0 * c.ncy0;
+    }
+    pre1[n] = (int32_t)s1;
+    pre2[n] = (int32_t)s2;
+    pre4[n] = (int32_t)s4;
+    pt2[n] = (int32_t)st2;
+    pt4[n] = (int32_t)st4;
+    pc[n] = (int32_t)sc;
+    P->px1 = s1;
+    P->px2 = s2;
+    P->px4 = s4;
+    P->t2 = st2;
+    P->t4 = st4;
+    P->cells = sc;
+    for (auto *v : {&pre1, &pre2, &pre4, &pt2, &pt4, &pc}) P->h_pre.insert(P->h_pre.end(), v->begin(), v->end());
+    int64_t at = 0;
+    P->off_wp2 = at;
+    at = align256(at + 32 * 9 * 16 * 2);
+    P->off_wp3 = at;
+    at = align256(at + 32 * 9 * 32 * 2);
+    P->off_a1 = at;
+    at = align256(at + s1 * 16 * 2);
+    P->off_a2 = at;
+    at = align256(at + s2 * 32 * 2);
+    P->off_a3 = at;
+    at = align256(at + s4 * 32 * 2);
+    P->off_g1 = at;
+    at = align256(at + s1 * 16 * 4);
+    P->off_g2 = at;
+    at = align256(at + s2 * 32 * 4);
+    P->off_g3 = at;
+    at = align256(at + s4 * 32 * 4);
+    P->off_dz = at;
+    at = align256(at + s4 * 4);
+    P->off_lz = at;
+    at = align256(at + s4 * 4);
+    P->off_part = at;
+    at = align256(at + (int64_t)CNN_PARTS * CNN_NPARAM * 4);
+    P->total = at;
+    if (hipMalloc((void **)&P->d_img, sizeof(CnnImg) * n) != hipSuccess ||
+        hipMemcpy(P->d_img, P->h_img.data(), sizeof(CnnImg) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc((void **)&P->d_pre, sizeof(int32_t) * P->h_pre.size()) != hipSuccess ||
+        hipMemcpy(P->d_pre, P->h_pre.data(), sizeof(int32_t) * P->h_pre.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        if (P->d_img) (void)hipFree(P->d_img);
+        if (P->d_pre) (void)hipFree(P->d_pre);
+        delete P;
+        return fail(VSFE_EHIP, "upload of the proposer tables failed");
+    }
+    b->cnn = P;
+    b->info_cnn.workspace_bytes = P->total;
+    b->info_cnn.grid_elems = s4;
+    b->info_cnn.n_params = CNN_NPARAM;
+    b->info_cnn.n_cells0 = sc;
+    return VSFE_OK;
+}
+
+void cnn_release(vsfe_batch *b) {
+    CnnPlan *P = (CnnPlan *)b->cnn;
+    if (!P) return;
+    if (P->d_img) (void)hipFree(P->d_img);
+    if (P->d_pre) (void)hipFree(P->d_pre);
+    delete P;
+    b->cnn = nullptr;
+}
+
+static int32_t cnn_common(const vsfe_ctx *ctx, const vsfe_batch *b, int32_t *status, CnnPlan **P) {
+    int32_t rc = check_common(ctx, b, status);
+    if (rc) return rc;
+    *P = (CnnPlan *)b->cnn;
+    if (!*P) return fail(VSFE_EINVAL, "the proposer needs at least 4 pyramid levels");
+    return VSFE_OK;
+}
+
+static int32_t run_forward(const vsfe_batch *b, const CnnPlan *P, const uint8_t *pyr, const uint16_t *prm,
+                           uint8_t *ws, float *z, hipStream_t st) {
+    const int n = P->n;
+    const int32_t *pre = P->d_pre;
+    uint16_t *wp2 = (uint16_t *)(ws + P->off_wp2), *wp3 = (uint16_t *)(ws + P->off_wp3);
+    uint16_t *a1 = (uint16_t *)(ws + P->off_a1), *a2 = (uint16_t *)(ws + P->off_a2), *a3 = (uint16_t *)(ws + P->off_a3);
+    hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, prm, wp2, wp3);
+    if (P->px1 > 0)
+        hipLaunchKernelGGL(cnn_conv1_kernel, dim3((unsigned)((P->px1 + 255) / 256)), dim3(256), 0, st, P->d_img, pre, n,
+                           P->px1, pyr, prm, a1);
+    if (P->t2 > 0)
+        hipLaunchKernelGGL((cnn_conv_mfma_kernel<16, false>), dim3((unsigned)((P->t2 + 3) / 4)), dim3(256), 0, st,
+                           P->d_img, pre + 3 * (n + 1), n, P->t2, a1, a2, wp2, prm, (float *)nullptr);
+    if (P->t4 > 0)
+        hipLaunchKernelGGL((cnn_conv_mfma_kernel<32, true>), dim3((unsigned)((P->t4 + 3) / 4)), dim3(256), 0, st,
+                           P->d_img, pre + 4 * (n + 1), n, P->t4, a2, a3, wp3, prm, z);
+    (void)b;
+    return check_launch("cnn forward");
+}
+
+}  // namespace vsfe
+
+using namespace vsfe;
+
+extern "C" {
+
+int32_t vsfe_cnn_info_get(const vsfe_batch *b, vsfe_cnn_info *out) {
+    if (!b || !out) return fail(VSFE_EINVAL, "null argument");
+    if (!b->cnn) return fail(VSFE_EINVAL, "the proposer needs at least 4 pyramid levels");
+    *out = b->info_cnn;
+    return VSFE_OK;
+}
+
+int32_t cnn_forward(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *pyr, const uint16_t *params_bf16,
+                    void *workspace, float *grid_logits, int32_t *status, void *stream) {
+    CnnPlan *P = nullptr;
+    int32_t rc = cnn_common(ctx, b, status, &P);
+    if (rc) return rc;
+    if (!pyr || !params_bf16 || !workspace || !grid_logits) return fail(VSFE_EINVAL, "null buffer");
+    return run_forward(b, P, pyr, params_bf16, (uint8_t *)workspace, grid_logits, (hipStream_t)stream);
+}
+
+int32_t cnn_propose(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *pyr, const uint16_t *params_bf16,
+                    float thresh, void *workspace, float *grid_logits, float *cell_logits, uint8_t *cell_mask,
+                    int32_t *status, void *stream) {
+    CnnPlan *P = nullptr;
+    int32_t rc = cnn_common(ctx, b, status, &P);
+    if (rc) return rc;
+    if (!pyr || !params_bf16 || !workspace || !grid_logits || !cell_mask) return fail(VSFE_EINVAL, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    rc = run_forward(b, P, pyr, params_bf16, (uint8_t *)workspace, grid_logits, st);
+    if (rc) return rc;
+    if (P->cells > 0)
+        hipLaunchKernelGGL(cnn_cells_kernel, dim3((unsigned)((P->cells + 255) / 256)), dim3(256), 0, st, P->d_img,
+                           P->d_pre + 5 * (P->n + 1), P->n, P->cells, grid_logits, thresh, cell_logits, cell_mask,
+                           ctx->scale_q16[3]);
+    return check_launch("cnn_propose");
+}
+
+int32_t cnn_backward(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *pyr, const uint16_t *params_bf16,
+                     void *workspace, const float *grid_logits, const float *grid_targets, float pos_weight,
+                     float *grad, float *loss, int32_t *status, void *stream) {
+    CnnPlan *P = nullptr;
+    int32_t rc = cnn_common(ctx, b, status, &P);
+    if (rc) return rc;
+    if (!pyr || !params_bf16 || !workspace || !grid_logits || !grid_targets || !grad)
+        return fail(VSFE_EINVAL, "null buffer");
+    if (!(pos_weight > 0.f)) return fail(VSFE_EINVAL, "pos_weight must be positive");
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t *ws = (uint8_t *)workspace;
+    const int n = P->n;
+    const int32_t *pre = P->d_pre;
+    uint16_t *a1 = (uint16_t *)(ws + P->off_a1), *a2 = (uint16_t *)(ws + P->off_a2), *a3 = (uint16_t *)(ws + P->off_a3);
+    float *g1 = (float *)(ws + P->off_g1), *g2 = (float *)(ws + P->off_g2), *g3 = (float *)(ws + P->off_g3);
+    float *dz = (float *)(ws + P->off_dz), *lz = (float *)(ws + P->off_lz), *part = (float *)(ws + P->off_part);
+    if (P->px4 <= 0) return fail(VSFE_EINVAL, "empty proposer grid");
+    hipLaunchKernelGGL(cnn_head_bwd_kernel, dim3((unsigned)((P->px4 + 255) / 256)), dim3(256), 0, st, P->px4,
+                       grid_logits, grid_targets, pos_weight, params_bf16, a3, dz, lz, g3);
+    hipLaunchKernelGGL(cnn_head_wgrad_kernel, dim3(CNN_PARTS), dim3(256), 0, st, P->px4, dz, a3, part);
+    hipLaunchKernelGGL((cnn_wgrad_kernel<32, 32, false>), dim3(CNN_PARTS, 4), dim3(256), 0, st, P->d_img,
+                       pre + 2 * (n + 1), n, P->px4, g3, a2, pyr, part, P_W3, P_B3);
+    hipLaunchKernelGGL((cnn_dgrad_kernel<32, 32>), dim3((unsigned)((P->px2 * 32 + 255) / 256)), dim3(256), 0, st,
+                       P->d_img, pre + 1 * (n + 1), n, P->px2, g3, a2, params_bf16, P_W3, g2);
+    hipLaunchKernelGGL((cnn_wgrad_kernel<16, 32, false>), dim3(CNN_PARTS, 2), dim3(256), 0, st, P->d_img,
+                       pre + 1 * (n + 1), n, P->px2, g2, a1, pyr, part, P_W2, P_B2);
+    hipLaunchKernelGGL((cnn_dgrad_kernel<16, 32>), dim3((unsigned)((P->px1 * 16 + 255) / 256)), dim3(256), 0, st,
+                       P->d_img, pre, n, P->px1, g2, a1, params_bf16, P_W2, g1);
+    hipLaunchKernelGGL((cnn_wgrad_kernel<1, 16, true>), dim3(CNN_PARTS), dim3(256), 0, st, P->d_img, pre, n, P->px1,
+                       g1, a1, pyr, part, P_W1, P_B1);
+    hipLaunchKernelGGL(cnn_reduce_kernel, dim3((CNN_NPARAM + 255) / 256), dim3(256), 0, st, part, grad, lz, P->px4,
+                       loss);
+    return check_launch("cnn_backward");
+}
+
+int32_t cnn_adam_step(float *params, uint16_t *params_bf16, float *m, float *v, const float *grad, int32_t n,
+                      float lr, float beta1, float beta2, float eps, int32_t step, void *stream) {
+    if (!params || !params_bf16 || !m || !v || !grad) return fail(VSFE_EINVAL, "null buffer");
+    if (n < 1 || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+        !(eps > 0.f))
+        return fail(VSFE_EINVAL, "bad optimizer arguments");
+    const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(cnn_adam_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, params_bf16,
+                       m, v, grad, n, lr, beta1, beta2, eps, c1, c2);
+    return check_launch("cnn_adam_step");
+}
+
+}  // extern "C"

@@ -95,6 +95,8 @@ struct vsfe_batch {
     std::vector<vsfe::CellChunk> h_chunks;
     vsfe::CellChunk *d_chunks = nullptr;
     bool pairs_ok = false;                       // even count, equal pair sizes
+    void *cnn = nullptr;                         // proposer plan (levels >= 4)
+    vsfe_cnn_info info_cnn{};
 };
 
 namespace vsfe {
@@ -103,6 +105,10 @@ void set_error(const std::string &msg);
 int32_t fail(int32_t code, const std::string &msg);
 int32_t check_launch(const char *what);
 int32_t check_common(const vsfe_ctx *ctx, const vsfe_batch *b, int32_t *status);
+
+// proposer geometry of a batch (no-op below 4 levels) and its release
+int32_t cnn_setup(vsfe_batch *b);
+void cnn_release(vsfe_batch *b);
 
 // one-time upload of the orientation disc tables to the current device
 int32_t orb_prepare(int device);

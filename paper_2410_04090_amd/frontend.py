@@ -54,6 +54,15 @@ class Frontend:
         self.status = torch.zeros(1, **i32)
         self.crf = torch.zeros(max(info.crf_elems, 1), dtype=torch.int16, device=dev) if with_crf else None
         self.cell_mask = torch.ones(max(info.n_cells0, 1), **u8) if with_mask else None
+        self.cnn = None
+        if self.params.n_levels >= 4:
+            ci = vsfe.cnn_info(self.batch)
+            self.cnn = ci
+            self.cnn_ws = torch.zeros(max(ci.workspace_bytes, 1), **u8)
+            self.grid_logits = torch.zeros(max(ci.grid_elems, 1), dtype=torch.float32, device=dev)
+            self.cell_logits = torch.zeros(max(ci.n_cells0, 1), dtype=torch.float32, device=dev)
+            if self.cell_mask is None:
+                self.cell_mask = torch.ones(max(info.n_cells0, 1), **u8)
         self.describe = True
         self.stereo = self.n % 2 == 0 and all(self.sizes[i] == self.sizes[i + 1] for i in range(0, self.n, 2))
         self._graph = None
@@ -89,17 +98,54 @@ class Frontend:
                 vsfe.stereo_match(c, b, self.kps, self.kp_count, self.desc, self.match_idx, self.match_dist,
                                   self.match_disp, self.status, stream)
 
-    def capture(self, **kw):
-        """Capture run() into a HIP graph on a side stream."""
+    def run_learned(self, params_bf16, thresh, stream=None, describe=None, stereo=None):
+        """Learned-proposal path: pyramid, CNN cell proposal on level 3,
+        detection gated to the proposed cells, then the unchanged rest."""
+        describe = self.describe if describe is None else describe
+        stereo = self.stereo if stereo is None else stereo
+        c, b = self.ctx, self.batch
+        vsfe.pyramid_build(c, b, self.images, self.pyr, self.status, stream)
+        vsfe.cnn_propose(c, b, self.pyr, params_bf16, thresh, self.cnn_ws, self.grid_logits, self.cell_logits,
+                         self.cell_mask, self.status, stream)
+        vsfe.fast_br_detect(c, b, self.images, self.pyr, self.cell_mask, self.cell_keys, self.crf, self.status,
+                            stream)
+        vsfe.pyca_cull_aggregate(c, b, self.cell_keys, self.workspace, self.kps, self.kp_count, self.status,
+                                 stream)
+        if describe:
+            vsfe.orb_describe(c, b, self.images, self.pyr, self.kps, self.kp_count, self.desc, self.status, stream)
+            if stereo:
+                vsfe.stereo_match(c, b, self.kps, self.kp_count, self.desc, self.match_idx, self.match_dist,
+                                  self.match_disp, self.status, stream)
+
+    def cnn_geometry(self, image):
+        """(W3, H3, Wz, Hz) of one image's proposer grid."""
+        li = self.level_info(image, 3)
+        w3, h3 = li.width, li.height
+        wz, hz = w3, h3
+        for _ in range(3):
+            wz, hz = (wz + 1) // 2, (hz + 1) // 2
+        return w3, h3, wz, hz
+
+    def grid_offsets(self):
+        offs, at = [], 0
+        for i in range(self.n):
+            _, _, wz, hz = self.cnn_geometry(i)
+            offs.append((at, hz, wz))
+            at += wz * hz
+        return offs
+
+    def capture(self, fn=None, **kw):
+        """Capture run() (or fn(stream=...)) into a HIP graph on a side stream."""
+        fn = self.run if fn is None else fn
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            self.run(stream=s, **kw)          # warm-up outside the graph
+            fn(stream=s, **kw)                # warm-up outside the graph
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
-            self.run(stream=s, **kw)
+            fn(stream=s, **kw)
         torch.cuda.synchronize()
         self._graph = g
         return g

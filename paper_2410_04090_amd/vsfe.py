@@ -56,10 +56,16 @@ class LevelInfo(C.Structure):
                 ("cell0_offset", C.c_int64)]
 
 
+class CnnInfo(C.Structure):
+    _fields_ = [("workspace_bytes", C.c_int64), ("grid_elems", C.c_int64), ("n_cells0", C.c_int64),
+                ("n_params", C.c_int32)]
+
+
 EXPORTS = ["vsfe_params_default", "vsfe_params_check", "vsfe_level_geometry", "vsfe_ctx_create",
            "vsfe_ctx_destroy", "vsfe_batch_create", "vsfe_batch_destroy", "vsfe_batch_plan",
            "vsfe_batch_info_get", "vsfe_batch_level_info", "vsfe_ctx_set_tile", "vsfe_last_error",
-           "pyramid_build", "fast_br_detect", "pyca_cull_aggregate", "orb_describe", "stereo_match"]
+           "pyramid_build", "fast_br_detect", "pyca_cull_aggregate", "orb_describe", "stereo_match",
+           "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step"]
 
 _lib = None
 
@@ -103,7 +109,13 @@ def lib():
     L.pyca_cull_aggregate.argtypes = [vp, vp, vp, vp, C.POINTER(KpSoa), vp, vp, vp]
     L.orb_describe.argtypes = [vp, vp, vp, vp, C.POINTER(KpSoa), vp, vp, vp, vp]
     L.stereo_match.argtypes = [vp, vp, C.POINTER(KpSoa), vp, vp, vp, vp, vp, vp, vp]
-    for f in ("pyramid_build", "fast_br_detect", "pyca_cull_aggregate", "orb_describe", "stereo_match"):
+    L.vsfe_cnn_info_get.argtypes = [vp, C.POINTER(CnnInfo)]
+    L.cnn_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.cnn_propose.argtypes = [vp, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp]
+    L.cnn_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_float, vp, vp, vp, vp]
+    L.cnn_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]
+    for f in ("pyramid_build", "fast_br_detect", "pyca_cull_aggregate", "orb_describe", "stereo_match",
+              "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -236,3 +248,32 @@ def stereo_match(ctx, b, kps, kp_count, desc, match_idx, match_dist, match_disp,
     s = kp_soa(kps)
     _check(lib().stereo_match(ctx, b, C.byref(s), _p(kp_count), _p(desc), _p(match_idx),
                               _p(match_dist), _p(match_disp), _p(status), _stream(stream)))
+
+
+# ------------------------------------------------------------- learned proposer
+def cnn_info(b) -> CnnInfo:
+    info = CnnInfo()
+    _check(lib().vsfe_cnn_info_get(b, C.byref(info)))
+    return info
+
+
+def cnn_forward(ctx, b, pyr, params_bf16, workspace, grid_logits, status, stream=None):
+    _check(lib().cnn_forward(ctx, b, _p(pyr), _p(params_bf16), _p(workspace), _p(grid_logits), _p(status),
+                             _stream(stream)))
+
+
+def cnn_propose(ctx, b, pyr, params_bf16, thresh, workspace, grid_logits, cell_logits, cell_mask, status,
+                stream=None):
+    _check(lib().cnn_propose(ctx, b, _p(pyr), _p(params_bf16), float(thresh), _p(workspace), _p(grid_logits),
+                             _p(cell_logits), _p(cell_mask), _p(status), _stream(stream)))
+
+
+def cnn_backward(ctx, b, pyr, params_bf16, workspace, grid_logits, grid_targets, pos_weight, grad, loss, status,
+                 stream=None):
+    _check(lib().cnn_backward(ctx, b, _p(pyr), _p(params_bf16), _p(workspace), _p(grid_logits), _p(grid_targets),
+                              float(pos_weight), _p(grad), _p(loss), _p(status), _stream(stream)))
+
+
+def cnn_adam_step(params, params_bf16, m, v, grad, lr, beta1, beta2, eps, step, stream=None):
+    _check(lib().cnn_adam_step(_p(params), _p(params_bf16), _p(m), _p(v), _p(grad), int(params.numel()),
+                               float(lr), float(beta1), float(beta2), float(eps), int(step), _stream(stream)))

@@ -1,0 +1,223 @@
+"""GPU parity of the learned cell proposer with its oracle.
+
+Forward logits (bfloat16 weights and activations, float32 sums) must match
+the oracle, which rounds at the same storage points, within 1e-2 absolute;
+cell logits and masks are exact functions of the grid logits; gradients
+and loss match the float64 oracle backward to a relative L2 tolerance; the
+gated exact path matches the oracle run on the GPU's mask bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn as ocnn
+from synth import pattern as pat
+from synth import scenes
+from synth.configs import Params
+from tests.parity_util import compare_kps, compare_matches, say
+
+pytestmark = pytest.mark.gpu
+
+LAYERS = [("w1", 0, 144), ("b1", 144, 160), ("w2", 160, 4768), ("b2", 4768, 4800), ("w3", 4800, 14016),
+          ("b3", 14016, 14048), ("w4", 14048, 14080), ("b4", 14080, 14081)]
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def theta_for(seed):
+    rng = np.random.default_rng(seed)
+    th = np.concatenate([p.reshape(-1) for p in pat.cnn_init(seed)]).astype(np.float64)
+    # non-zero biases so that every ReLU regime is exercised
+    for name, a, b in LAYERS:
+        if name.startswith("b"):
+            th[a:b] = rng.normal(0, 0.1, b - a)
+    return th
+
+
+def bf16_tensor(torch, theta):
+    return torch.tensor(theta, dtype=torch.float32).to(torch.bfloat16).view(torch.int16).cuda()
+
+
+def make_batch(torch, imgs, params):
+    from paper_2410_04090_amd.frontend import Frontend
+    fe = Frontend(params, [(im.shape[1], im.shape[0]) for im in imgs], pat.brief_pattern())
+    fe.upload(imgs)
+    return fe
+
+
+def grid_of(fe, z_all, i):
+    off, hz, wz = fe.grid_offsets()[i]
+    return z_all[off:off + hz * wz].reshape(hz, wz)
+
+
+def images_mixed():
+    a, b = scenes.stereo_pair(4001, 1241, 376, 200, 64)
+    c = scenes.random_image(4002, 333, 201)
+    return [a, b, c, scenes.mono_image(4003, 333, 201, 60)]
+
+
+def test_forward_matches_oracle(torch_mod):
+    torch = torch_mod
+    imgs = images_mixed()
+    p = Params()
+    theta = theta_for(11)
+    fe = make_batch(torch, imgs, p)
+    try:
+        say("cnn forward on", [im.shape for im in imgs])
+        fe.run(describe=False)
+        w = bf16_tensor(torch, theta)
+        from paper_2410_04090_amd import vsfe
+        vsfe.cnn_forward(fe.ctx, fe.batch, fe.pyr, w, fe.cnn_ws, fe.grid_logits, fe.status)
+        torch.cuda.synchronize()
+        z = fe.grid_logits.cpu().numpy()
+        for i, img in enumerate(imgs):
+            lv3 = oracle.pyramid(img, 4)[3]
+            ref, _ = ocnn.forward(lv3, theta, bf16=True)
+            got = grid_of(fe, z, i)
+            assert got.shape == ref.shape
+            err = np.abs(got - ref).max()
+            say("image", i, "max |dz| =", err, "range", ref.min(), ref.max())
+            assert err <= 1e-2
+            assert np.std(ref) > 0.05          # the test network is not degenerate
+    finally:
+        fe.close()
+
+
+def test_propose_cells_and_mask(torch_mod):
+    torch = torch_mod
+    imgs = images_mixed()[:2]
+    p = Params()
+    theta = theta_for(12)
+    fe = make_batch(torch, imgs, p)
+    try:
+        from paper_2410_04090_amd import vsfe
+        fe.run(describe=False)
+        w = bf16_tensor(torch, theta)
+        z_all = None
+        for thresh in (-0.5, 0.0, 0.7):
+            vsfe.cnn_propose(fe.ctx, fe.batch, fe.pyr, w, thresh, fe.cnn_ws, fe.grid_logits, fe.cell_logits,
+                             fe.cell_mask, fe.status)
+            torch.cuda.synchronize()
+            z_all = fe.grid_logits.cpu().numpy()
+            cl = fe.cell_logits.cpu().numpy()
+            mk = fe.cell_mask.cpu().numpy()
+            at = 0
+            for i, img in enumerate(imgs):
+                H, W = img.shape
+                ref = ocnn.cell_logits(grid_of(fe, z_all, i), W, H).reshape(-1)
+                got = cl[at:at + ref.size]
+                assert np.array_equal(got, ref.astype(np.float32))
+                assert np.array_equal(mk[at:at + ref.size], (ref >= thresh).astype(np.uint8))
+                at += ref.size
+    finally:
+        fe.close()
+
+
+def test_backward_matches_oracle(torch_mod):
+    torch = torch_mod
+    imgs = [scenes.mono_image(4010, 640, 480, 120), scenes.random_image(4011, 420, 300)]
+    p = Params()
+    theta = theta_for(13)
+    fe = make_batch(torch, imgs, p)
+    try:
+        from paper_2410_04090_amd import vsfe
+        fe.run(describe=False)
+        w = bf16_tensor(torch, theta)
+        vsfe.cnn_forward(fe.ctx, fe.batch, fe.pyr, w, fe.cnn_ws, fe.grid_logits, fe.status)
+        rng = np.random.default_rng(3)
+        n = int(fe.cnn.grid_elems)
+        t = (rng.random(n) < 0.6).astype(np.float32)
+        tgt = torch.tensor(t).cuda()
+        grad = torch.zeros(ocnn.N_PARAMS, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        vsfe.cnn_backward(fe.ctx, fe.batch, fe.pyr, w, fe.cnn_ws, fe.grid_logits, tgt, 1.7, grad, loss, fe.status)
+        torch.cuda.synchronize()
+        g_gpu = grad.cpu().numpy().astype(np.float64)
+        # oracle: mean BCE over all positions of the batch
+        zs, caches = [], []
+        for img in imgs:
+            z, cache = ocnn.forward(oracle.pyramid(img, 4)[3], theta, bf16=True)
+            zs.append(z)
+            caches.append(cache)
+        zcat = np.concatenate([z.reshape(-1) for z in zs])
+        ref_loss, dz = ocnn.bce_with_logits(zcat, t, pos_weight=1.7)
+        g_ref = np.zeros(ocnn.N_PARAMS)
+        at = 0
+        for z, cache in zip(zs, caches):
+            g_ref += ocnn.backward(cache, dz[at:at + z.size].reshape(z.shape))
+            at += z.size
+        say("loss gpu", float(loss.item()), "oracle", ref_loss)
+        assert abs(float(loss.item()) - ref_loss) <= 2e-3 * ref_loss
+        for name, a, b in LAYERS:
+            num = np.linalg.norm(g_gpu[a:b] - g_ref[a:b])
+            den = np.linalg.norm(g_ref[a:b]) + 1e-12
+            say("grad", name, "rel err", num / den)
+            assert num / den <= 2e-2, name
+        # deterministic: a second backward gives the same bits
+        grad2 = torch.zeros_like(grad)
+        vsfe.cnn_backward(fe.ctx, fe.batch, fe.pyr, w, fe.cnn_ws, fe.grid_logits, tgt, 1.7, grad2, loss, fe.status)
+        torch.cuda.synchronize()
+        assert torch.equal(grad, grad2)
+    finally:
+        fe.close()
+
+
+def test_adam_step(torch_mod):
+    torch = torch_mod
+    from paper_2410_04090_amd import vsfe
+    rng = np.random.default_rng(4)
+    n = ocnn.N_PARAMS
+    w0 = rng.normal(size=n).astype(np.float32)
+    g = rng.normal(size=n).astype(np.float32)
+    w = torch.tensor(w0).cuda()
+    wb = torch.zeros(n, dtype=torch.int16, device="cuda")
+    m = torch.zeros(n, device="cuda")
+    v = torch.zeros(n, device="cuda")
+    gt = torch.tensor(g).cuda()
+    mm, vv, ww = np.zeros(n), np.zeros(n), w0.astype(np.float64)
+    for step in (1, 2, 3):
+        vsfe.cnn_adam_step(w, wb, m, v, gt, 1e-3, 0.9, 0.999, 1e-8, step)
+        mm = 0.9 * mm + 0.1 * g
+        vv = 0.999 * vv + 0.001 * g.astype(np.float64) ** 2
+        ww = ww - 1e-3 * (mm / (1 - 0.9 ** step)) / (np.sqrt(vv / (1 - 0.999 ** step)) + 1e-8)
+    torch.cuda.synchronize()
+    assert np.allclose(w.cpu().numpy(), ww, atol=1e-5)
+    assert np.array_equal(wb.view(torch.bfloat16).float().cpu().numpy(),
+                          ocnn.bf16_round(w.cpu().numpy()).astype(np.float32))
+
+
+def test_learned_path_matches_oracle_on_gpu_mask(torch_mod):
+    """The gated exact path equals the oracle run with the GPU's cell mask."""
+    torch = torch_mod
+    l, r = scenes.stereo_pair(4020, 640, 360, 120, 40)
+    p = Params()
+    theta = theta_for(14)
+    fe = make_batch(torch, [l, r], p)
+    try:
+        w = bf16_tensor(torch, theta)
+        fe.run_learned(w, 0.0)
+        torch.cuda.synchronize()
+        cl = fe.cell_logits.cpu().numpy()
+        tau = float(np.median(cl[np.isfinite(cl)]))      # keeps about half of the cells
+        fe.run_learned(w, tau)
+        torch.cuda.synchronize()
+        mk = fe.cell_mask.cpu().numpy()
+        at = 0
+        refs = []
+        for i, img in enumerate((l, r)):
+            ncx, ncy = (640 + 31) // 32, (360 + 31) // 32
+            m0 = mk[at:at + ncx * ncy].reshape(ncy, ncx)
+            at += ncx * ncy
+            assert 0 < m0.sum() < m0.size          # a real gate: some cells on, some off
+            _, ref = oracle.frontend_image(img, p, pat.brief_pattern(), cell_mask0=m0)
+            compare_kps(ref, fe.results(i), i)
+            refs.append(ref)
+        compare_matches(fe, 0, refs[0], refs[1], p)
+    finally:
+        fe.close()
