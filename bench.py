@@ -24,6 +24,11 @@ import numpy as np  # noqa: E402
 
 METRIC = "stereo frames/s, exact vs learned-proposal path at ≥99% keypoint recall"
 HBM_PEAK_GBS = 8000.0
+PKG = os.path.join(ROOT, "paper_2410_04090_amd")
+# source file of each call's kernels (a stored counter reading is valid only
+# for the source it was taken from)
+CALL_SOURCE = {"pyramid_build": "pyramid.hip", "fast_br_detect": "detect.hip", "pyca_cull_aggregate": "pyca.hip",
+               "orb_describe": "orb.hip", "stereo_match": "stereo.hip"}
 
 
 def _gen_pair(args):
@@ -69,6 +74,71 @@ def time_call(fn, reps, stream):
     return e0.elapsed_time(e1) * 1000.0 / reps
 
 
+def source_sha(call):
+    import hashlib
+    paths = [os.path.join(PKG, "csrc", CALL_SOURCE[call]), os.path.join(PKG, "csrc", "vsfe_internal.h")]
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(call, workload):
+    """HBM bytes per launch of `call` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration), or None
+    when there is none or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.txt" % (call, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_sha(call):
+        return None
+    try:
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    byte counters (run under the counter profiler)."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 5}), flush=True)
+
+
+def load_proposer(path):
+    d = np.load(path, allow_pickle=False)
+    meta = json.loads(str(d["meta"])) if "meta" in d else {}
+    return d["params"].astype(np.float32), meta
+
+
+def keypoint_sets(fe):
+    import torch
+    torch.cuda.synchronize()
+    counts = fe.kp_count.cpu().numpy()
+    n_max = fe.params.n_max
+    lv = fe.kps["level"].cpu().numpy()
+    xx = fe.kps["x"].cpu().numpy().view(np.uint16)
+    yy = fe.kps["y"].cpu().numpy().view(np.uint16)
+    out = []
+    for i in range(fe.n):
+        s = slice(i * n_max, i * n_max + int(counts[i]))
+        out.append(set(zip(lv[s].tolist(), xx[s].tolist(), yy[s].tolist())))
+    return out
+
+
 def cpu_baseline(wl, imgs, pattern, budget_s):
     import oracle
     n_pairs = len(imgs) // 2
@@ -86,6 +156,62 @@ def cpu_baseline(wl, imgs, pattern, budget_s):
                       % (done, n_pairs, w, h, dt)}
 
 
+def learned_path(args, fe, sizes, stream, exact_value):
+    """Learned-proposal path on the same batch: CNN cell proposal on level 3,
+    detection only in proposed cells, the rest unchanged.  Recall and
+    precision are measured against the exact path's keypoints of this batch;
+    the threshold was calibrated on held-out scenes of the same size."""
+    import torch
+    from paper_2410_04090_amd import vsfe
+    if len(set(sizes)) != 1 or fe.cell_mask is None:
+        return None
+    w, h = sizes[0]
+    path = args.proposer or os.path.join(PKG, "weights", "proposer_%dx%d.npz" % (w, h))
+    if not os.path.exists(path):
+        print("no proposer weights for %dx%d, learned path skipped" % (w, h), file=sys.stderr, flush=True)
+        return None
+    theta, meta = load_proposer(path)
+    tau = meta.get("thresholds", {}).get("%dx%d" % (w, h))
+    if tau is None:
+        return None
+    wb = torch.from_numpy(theta).cuda().to(torch.bfloat16).view(torch.int16).contiguous()
+    fe.run()
+    exact = keypoint_sets(fe)
+    fe.run_learned(wb, tau)
+    got = keypoint_sets(fe)
+    kept = float(fe.cell_mask.float().mean().item())
+    ref_n = sum(len(r) for r in exact)
+    hit = sum(len(r & g) for r, g in zip(exact, got))
+    g2 = fe.capture(fe.run_learned, params_bf16=wb, thresh=tau)
+    for _ in range(args.warmup):
+        g2.replay()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        g2.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    c, b = fe.ctx, fe.batch
+    calls = {
+        "cnn_propose": lambda: vsfe.cnn_propose(c, b, fe.pyr, wb, tau, fe.cnn_ws, fe.grid_logits, fe.cell_logits,
+                                                fe.cell_mask, fe.status, stream),
+        "fast_br_detect_gated": lambda: vsfe.fast_br_detect(c, b, fe.images, fe.pyr, fe.cell_mask, fe.cell_keys,
+                                                            None, fe.status, stream),
+    }
+    ones = torch.ones_like(fe.cell_mask)
+    calls["fast_br_detect_all_cells_kept"] = lambda: vsfe.fast_br_detect(c, b, fe.images, fe.pyr, ones, fe.cell_keys,
+                                                                         None, fe.status, stream)
+    call_us = {k: round(time_call(f, args.kernel_reps, stream), 2) for k, f in calls.items()}
+    value = (len(sizes) // 2) * 1000.0 / ms
+    return {"value": round(value, 1), "unit": "stereo pairs/s", "ms_per_step": round(ms, 4),
+            "speedup_vs_exact": round(value / exact_value, 4), "recall": round(hit / max(ref_n, 1), 5),
+            "precision": round(hit / max(sum(len(g) for g in got), 1), 5), "kept_cell_frac": round(kept, 4),
+            "thresh": tau, "weights": os.path.relpath(path, ROOT), "calls_us": call_us}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,7 +222,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--proposer", default=None, help="proposer weights (default: the packaged ones for the image size)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); pairs are independent, "
               "see DESIGN.md for how the batch would shard across GPUs", file=sys.stderr)
@@ -122,6 +256,11 @@ def main():
     torch.cuda.synchronize()
     assert int(fe.status.item()) == 0, "device status flagged"
     print("first run ok", file=sys.stderr, flush=True)
+
+    tune = None
+    if not args.no_autotune:
+        tune = fe.autotune(reps=3)
+        print("autotuned tiles w=%s h=%s" % (tune["tile_w"], tune["tile_h"]), file=sys.stderr, flush=True)
 
     # ---- timed region: K graph replays of the whole exact path
     g = fe.capture()
@@ -187,9 +326,11 @@ def main():
     }
     dominant = max(call_us, key=call_us.get)
     ach = alg[dominant] / (call_us[dominant] * 1e-6) / 1e9
+    traffic = stored_traffic(dominant, args.workload)
     roof = {"kernel": dominant, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-            "alg_bytes_per_launch": int(alg[dominant]), "avg_launch_us": round(call_us[dominant], 2)}
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_launch": int(alg[dominant]), "avg_launch_us": round(call_us[dominant], 2),
+            "source_sha": source_sha(dominant)}
     path_bytes = sum(alg.values())
     res = {
         "metric": METRIC, "value": round(value, 1), "unit": "stereo pairs/s", "n_gpus": 1,
@@ -204,6 +345,11 @@ def main():
         "path_hbm_frac": round(path_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "keypoints_per_image": round(n_kp / len(sizes), 1),
     }
+    if tune is not None:
+        res["autotune"] = tune
+    learned = None if args.no_learned else learned_path(args, fe, sizes, stream, value)
+    if learned is not None:
+        res["learned"] = learned
     fe.close()
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(wl, imgs, pattern, args.cpu_budget)

@@ -165,6 +165,41 @@ int32_t vsfe_batch_level_info(const vsfe_batch *b, int32_t image, int32_t level,
  * 8 <= th <= 32. */
 int32_t vsfe_ctx_set_tile(vsfe_ctx *ctx, int32_t tile_w, int32_t tile_h);
 
+/* ------------------------------------------------------- batch autotuner */
+
+/* Outcome of vsfe_batch_autotune, per pyramid level l < n_levels. */
+typedef struct {
+    int32_t n_levels;
+    int32_t tile_w[VSFE_MAX_LEVELS];   /* chosen detector tile, pixels (whole cells) */
+    int32_t tile_h[VSFE_MAX_LEVELS];
+    float us[VSFE_MAX_LEVELS];         /* mean launch time of the chosen shape, microseconds */
+    float us_before[VSFE_MAX_LEVELS];  /* ... of the shape the batch had before tuning */
+    int32_t n_tried[VSFE_MAX_LEVELS];  /* distinct shapes timed */
+} vsfe_tune_report;
+
+/* Per-level detector tile extents of a batch (host arrays of n_levels
+ * entries).  A tile of tw x th pixels at level l packs
+ * min(32, max(1, tw / cell_l)) x min(16, max(1, th / cell_l)) cells.
+ * Results never depend on the tiles.  set: EINVAL unless every level has
+ * 8 <= tw <= 128 and 8 <= th <= 32; synchronises the device and replaces
+ * the batch's detector work table, so HIP graphs captured earlier with this
+ * batch must be captured again. */
+int32_t vsfe_batch_tiles_get(const vsfe_batch *b, int32_t *tile_w, int32_t *tile_h);
+int32_t vsfe_batch_set_tiles(vsfe_batch *b, const int32_t *tile_w, const int32_t *tile_h);
+
+/* Batching autotuner.  For every pyramid level, times fast_br_detect (no
+ * cell mask) over that level of every image of the batch for each distinct
+ * whole-cell tile shape that fits the detector's 128 x 32 pixel block (one
+ * warm-up and `reps` timed launches each, HIP events on `stream`), keeps the
+ * fastest per level and installs it as by vsfe_batch_set_tiles.  `images`
+ * and `pyr` must hold the batch's data with the pyramid built; `cell_keys`
+ * (n_cells entries) is overwritten.  Set-up call: synchronous, allocates a
+ * temporary table, not capturable.  Errors: EINVAL (null pointers, reps
+ * outside 1..1000), EHIP. */
+int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *images,
+                            const uint8_t *pyr, uint32_t *cell_keys, int32_t *status,
+                            int32_t reps, void *stream, vsfe_tune_report *out);
+
 /* Last error message of the calling thread ("" if none). */
 const char *vsfe_last_error(void);
 
@@ -185,8 +220,10 @@ int32_t pyramid_build(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *i
  * falling back to eps_lo corners (bit VSFE_KEY_FALLBACK) when the cell has
  * no eps_hi corner.  cell_keys (n_cells, written, 0 = empty).
  * cell_mask (n_cells0 bytes, nullable): learned gating, a level-l cell runs
- * only if its native-scale footprint overlaps a non-zero level-0 cell.
- * crf_debug (crf_elems, nullable): per-pixel eps_hi response, 0 elsewhere. */
+ * only if its native-scale footprint overlaps a non-zero level-0 cell; the
+ * keys of other cells are 0.
+ * crf_debug (crf_elems, nullable): per-pixel eps_hi response, 0 elsewhere
+ * (and 0 in cells that a cell_mask skips). */
 int32_t fast_br_detect(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
                        const uint8_t *pyr, const uint8_t *cell_mask, uint32_t *cell_keys,
                        uint16_t *crf_debug, int32_t *status, void *stream);

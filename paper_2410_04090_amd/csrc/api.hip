@@ -207,20 +207,12 @@ static int32_t plan_batch(const vsfe_params &p, int tile_w, int tile_h, int32_t 
         }
     }
     b->pyr_start[L] = (int32_t)b->h_pyr_items.size();
-    // detector tiles: whole cells, about tile_w x tile_h pixels
-    b->h_det_items.clear();
-    for (int i = 0; i < n; i++)
-        for (int l = 0; l < L; l++) {
-            const LevelDev &lv = b->images[i].lv[l];
-            // at most 32 x 16 cells and 128 x 64 pixels per tile (LDS budget of the detector)
-            const int nkx = std::min(32, std::max(1, tile_w / lv.cell));
-            const int nky = std::min(16, std::max(1, tile_h / lv.cell));
-            for (int cy = 0; cy < lv.ncy; cy += nky)
-                for (int cx = 0; cx < lv.ncx; cx += nkx)
-                    b->h_det_items.push_back(DetItem{(uint16_t)i, (uint16_t)l, (uint16_t)cx, (uint16_t)cy,
-                                                     (uint16_t)std::min(nkx, lv.ncx - cx),
-                                                     (uint16_t)std::min(nky, lv.ncy - cy), 0, 0});
-        }
+    // detector tiles: whole cells, about tile_w x tile_h pixels at every level
+    for (int l = 0; l < L; l++) {
+        b->tile_w[l] = tile_w;
+        b->tile_h[l] = tile_h;
+    }
+    det_items_build(b);
     b->h_chunks.clear();
     for (int i = 0; i < n; i++)
         for (int l = 0; l < L; l++) {
@@ -392,6 +384,7 @@ int32_t vsfe_batch_destroy(vsfe_batch *b) {
     if (b->d_coord) (void)hipFree(b->d_coord);
     if (b->d_det_items) (void)hipFree(b->d_det_items);
     if (b->d_chunks) (void)hipFree(b->d_chunks);
+    if (b->d_run) (void)hipFree(b->d_run);
     cnn_release(b);
     delete b;
     return VSFE_OK;
@@ -422,6 +415,8 @@ int32_t vsfe_batch_create(const vsfe_ctx *ctx, int32_t n, const int32_t *widths,
     if (!rc) rc = upload(b->h_coord, &b->d_coord);
     if (!rc) rc = upload(b->h_det_items, &b->d_det_items);
     if (!rc) rc = upload(b->h_chunks, &b->d_chunks);
+    if (!rc && b->info.n_cells > 0 && hipMalloc((void **)&b->d_run, (size_t)b->info.n_cells) != hipSuccess)
+        rc = fail(VSFE_EHIP, "hipMalloc of the run-flag table failed");
     if (!rc) rc = cnn_setup(b);
     if (rc) {
         vsfe_batch_destroy(b);

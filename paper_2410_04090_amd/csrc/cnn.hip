@@ -9,12 +9,15 @@
 // vector, OIHW weights followed by biases per layer.  Weights and stored
 // activations are bfloat16 (NHWC), sums are float32.
 //
-//  * conv1 (K = 9) runs on the VALU, one thread per output pixel;
+//  * conv1 (K = 9 taps, padded to 16) runs on v_mfma_f32_16x16x16_bf16;
 //  * conv2 (K = 144) and conv3 (K = 288) are implicit GEMMs on
 //    v_mfma_f32_16x16x32_bf16: one wave computes 16 output pixels x 32
 //    channels, each lane feeding 8 consecutive channels of one tap as its
 //    K slice (weights repacked to [co][tap][ci]); the 1x1 head is fused in
 //    conv3's epilogue with a 16-lane shuffle reduction;
+//  * inference (cnn_propose) runs the three layers and the head fused in
+//    one kernel per 4 x 8 tile of grid positions, activations in LDS; the
+//    layer-by-layer kernels (cnn_forward) keep the activations for training;
 //  * cell logits: per native-scale cell, the maximum over the grid
 //    positions whose projected centre ((8 j + 4) S_3 + 2^15) >> 16 falls in
 //    it (a cell with none is always kept);
@@ -44,9 +47,10 @@ struct CnnPlan {
     int n = 0;
     std::vector<CnnImg> h_img;
     CnnImg *d_img = nullptr;
-    std::vector<int32_t> h_pre;        // prefixes (n + 1 each): px1, px2, px4, tiles2, tiles4, cells
+    // prefixes (n + 1 each): px1, px2, px4, tiles2, tiles4, cells, tiles1, fused tiles
+    std::vector<int32_t> h_pre;
     int32_t *d_pre = nullptr;
-    int64_t px1 = 0, px2 = 0, px4 = 0, t2 = 0, t4 = 0, cells = 0;
+    int64_t px1 = 0, px2 = 0, px4 = 0, t2 = 0, t4 = 0, cells = 0, t1 = 0, tf = 0;
     int64_t off_wp2 = 0, off_wp3 = 0, off_a1 = 0, off_a2 = 0, off_a3 = 0, off_g1 = 0, off_g2 = 0, off_g3 = 0,
             off_dz = 0, off_lz = 0, off_part = 0, total = 0;
 };
@@ -82,40 +86,59 @@ __global__ void cnn_pack_kernel(const uint16_t *__restrict__ prm, uint16_t *__re
     }
 }
 
-__global__ __launch_bounds__(256) void cnn_conv1_kernel(const CnnImg *__restrict__ imgs, const int32_t *__restrict__ pre,
-                                                        int n, int64_t total, const uint8_t *__restrict__ pyr,
+// conv1 (1 -> 16, K = 9 taps) on v_mfma_f32_16x16x16_bf16: M = 16 output
+// pixels, N = 16 channels, K = the 9 taps zero-padded to 16; lane l feeds
+// taps 4 (l / 16) .. 4 (l / 16) + 3 of pixel l % 16.  The input x = (I - 128)
+// / 128 is exact in bfloat16.  Both forward paths use these helpers, so
+// their conv1 outputs are identical.
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t x_bf(int v) { return to_bf((float)(v - 128) * (1.0f / 128.0f)); }
+
+// this lane's B operand: w1[n][k] for its 4 taps k (0 beyond the ninth)
+__device__ __forceinline__ i16x4 conv1_weights(const uint16_t *prm, int lane) {
+    const int n = lane & 15, k0 = 4 * (lane >> 4);
+    i16x4 b;
+#pragma unroll
+    for (int j = 0; j < 4; j++) b[j] = (short)(k0 + j < 9 ? prm[P_W1 + n * 9 + k0 + j] : 0);
+    return b;
+}
+
+__device__ __forceinline__ f32x4 conv1_mfma(i16x4 a, i16x4 b) {
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, zero, 0, 0, 0);
+}
+
+// One wave: 16 consecutive conv1 pixels of one image (row-major), NHWC out.
+__global__ __launch_bounds__(256) void cnn_conv1_kernel(const CnnImg *__restrict__ imgs,
+                                                        const int32_t *__restrict__ pre_tiles, int n,
+                                                        int64_t total_tiles, const uint8_t *__restrict__ pyr,
                                                         const uint16_t *__restrict__ prm, uint16_t *__restrict__ a1) {
-    __shared__ float s_w[160];
-    if (threadIdx.x < 160) s_w[threadIdx.x] = bf(prm[threadIdx.x]);
-    __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= total) return;
-    const int i = find_image(pre, n, g);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    if (tile >= total_tiles) return;
+    const int i = find_image(pre_tiles, n, tile);
     const CnnImg im = imgs[i];
-    const int p = (int)(g - im.px1);
-    const int oy = p / im.w1, ox = p - oy * im.w1;
-    float x[9];
+    const int npx = im.w1 * im.h1;
+    const int p0 = (int)(tile - pre_tiles[i]) * 16;
+    const int m = lane & 15, grp = lane >> 4;
+    const int pm = p0 + m;
+    const int oy = pm / im.w1, ox = pm - oy * im.w1;
+    i16x4 a;
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
+    for (int j = 0; j < 4; j++) {
+        const int k = 4 * grp + j;
         const int iy = 2 * oy + k / 3 - 1, ix = 2 * ox + k % 3 - 1;
-        x[k] = (iy >= 0 && iy < im.h3 && ix >= 0 && ix < im.w3)
-                   ? ((float)pyr[im.lvl3 + (int64_t)iy * im.pitch3 + ix] - 128.0f) * (1.0f / 128.0f)
-                   : 0.0f;
+        const bool in = pm < npx && k < 9 && iy >= 0 && iy < im.h3 && ix >= 0 && ix < im.w3;
+        a[j] = (short)(in ? x_bf(pyr[im.lvl3 + (int64_t)iy * im.pitch3 + ix]) : 0);
     }
-    uint32_t packed[8];
+    const f32x4 acc = conv1_mfma(a, conv1_weights(prm, lane));
+    const float bias = bf(prm[P_B1 + m]);
 #pragma unroll
-    for (int co = 0; co < 16; co += 2) {
-        float s0 = s_w[P_B1 + co], s1 = s_w[P_B1 + co + 1];
-#pragma unroll
-        for (int k = 0; k < 9; k++) {
-            s0 += s_w[co * 9 + k] * x[k];
-            s1 += s_w[(co + 1) * 9 + k] * x[k];
-        }
-        packed[co / 2] = (uint32_t)to_bf(fmaxf(s0, 0.0f)) | ((uint32_t)to_bf(fmaxf(s1, 0.0f)) << 16);
+    for (int r = 0; r < 4; r++) {
+        const int p = p0 + 4 * grp + r;
+        if (p < npx) a1[(im.px1 + p) * 16 + m] = to_bf(fmaxf(acc[r] + bias, 0.0f));
     }
-    uint4 *dst = (uint4 *)(a1 + (int64_t)g * 16);
-    dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-    dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
 }
 
 // Implicit-GEMM 3x3 stride-2 convolution CIN -> 32 on MFMA; with HEAD the
@@ -189,6 +212,189 @@ __global__ __launch_bounds__(256) void cnn_conv_mfma_kernel(const CnnImg *__rest
             for (int r = 0; r < 4; r++) {
                 const int p = p0 + 4 * grp + r;
                 if (p < npx) z[out_base + p] = part[r] + b4;
+            }
+        }
+    }
+}
+
+// Fused inference forward: one 256-thread block computes a 4 x 8 tile of
+// grid logits with every intermediate activation in LDS (level-3 input
+// 39 x 71, conv1 19 x 35 x 16, conv2 9 x 17 x 32; positions outside an
+// activation map are its zero padding).  Same operand layout, chunk order
+// and rounding points as the layer-by-layer kernels, so the logits are
+// bit-identical to cnn_forward's.
+constexpr int CF3H = 4, CF3W = 8;                         // grid positions per tile
+constexpr int CF2H = 2 * CF3H + 1, CF2W = 2 * CF3W + 1;   // conv2 window  9 x 17
+constexpr int CF1H = 2 * CF2H + 1, CF1W = 2 * CF2W + 1;   // conv1 window 19 x 35
+constexpr int CF0H = 2 * CF1H + 1, CF0W = 2 * CF1W + 1;   // input window 39 x 71
+constexpr int CF0S = CF0W + 1;                            // input row stride (u16)
+constexpr int CF0D = (CF0W + 1 + 3) / 4;                  // dwords per input row (18)
+constexpr int CF_LD = (CF0H * CF0D + 255) / 256;          // dword loads per thread (3)
+constexpr int CF1N = CF1H * CF1W, CF2N = CF2H * CF2W;
+constexpr int CF_U = CF2N * 32 > CF0H * CF0S ? CF2N * 32 : CF0H * CF0S;
+
+__global__ __launch_bounds__(256) void cnn_fused_fwd_kernel(const CnnImg *__restrict__ imgs,
+                                                            const int32_t *__restrict__ pre_tiles, int n,
+                                                            const uint8_t *__restrict__ pyr,
+                                                            const uint16_t *__restrict__ prm,
+                                                            const uint16_t *__restrict__ wp2,
+                                                            const uint16_t *__restrict__ wp3, float *__restrict__ z) {
+    __shared__ __attribute__((aligned(16))) uint16_t s_a1[CF1N * 16];
+    __shared__ __attribute__((aligned(16))) uint16_t s_u[CF_U];     // input, then conv2 output
+    uint16_t *const s_c2 = s_u;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m = lane & 15, grp = lane >> 4;
+    const int i = find_image(pre_tiles, n, blockIdx.x);
+    const CnnImg im = imgs[i];
+    const int lt = (int)blockIdx.x - pre_tiles[i];
+    const int ntx = (im.w4 + CF3W - 1) / CF3W;
+    const int Y3 = (lt / ntx) * CF3H, X3 = (lt % ntx) * CF3W;
+    const int Y2 = 2 * Y3 - 1, X2 = 2 * X3 - 1, Y1 = 2 * Y2 - 1, X1 = 2 * X2 - 1, Y0 = 2 * Y1 - 1, X0 = 2 * X1 - 1;
+
+    // A. level-3 input window as bfloat16.  X0 - 1 = 8 X3 - 8 is a multiple
+    //    of 4 and rows start on 64-byte boundaries, so the window is read as
+    //    aligned dwords (bytes past the level width are masked); all loads
+    //    are issued before any is used.
+    {
+        uint32_t v[CF_LD];
+#pragma unroll
+        for (int k = 0; k < CF_LD; k++) {
+            const int d = tid + 256 * k;
+            const int rr = d / CF0D, j = d - rr * CF0D;
+            const int gy = Y0 + rr, gx = X0 - 1 + 4 * j;
+            const bool ok = d < CF0H * CF0D && gy >= 0 && gy < im.h3 && gx >= 0 && gx < im.w3;
+            v[k] = ok ? *(const uint32_t *)(pyr + im.lvl3 + (int64_t)gy * im.pitch3 + gx) : 0u;
+            if (ok && gx + 4 > im.w3) v[k] &= 0xFFFFFFFFu >> (8 * (gx + 4 - im.w3));
+        }
+#pragma unroll
+        for (int k = 0; k < CF_LD; k++) {
+            const int d = tid + 256 * k;
+            if (d >= CF0H * CF0D) continue;
+            const int rr = d / CF0D, j = d - rr * CF0D;
+            const int gy = Y0 + rr, gx = X0 - 1 + 4 * j;
+            const bool ok = gy >= 0 && gy < im.h3 && gx >= 0 && gx < im.w3;
+#pragma unroll
+            for (int bb = 0; bb < 4; bb++) {
+                const int cc = 4 * j - 1 + bb;                  // window column of byte bb
+                if (cc < 0 || cc >= CF0W) continue;
+                s_u[rr * CF0S + cc] = ok && gx + bb < im.w3 ? x_bf((int)((v[k] >> (8 * bb)) & 255u)) : (uint16_t)0;
+            }
+        }
+    }
+    __syncthreads();
+
+    // B. conv1
+    {
+        const i16x4 b = conv1_weights(prm, lane);
+        const float bias = bf(prm[P_B1 + m]);
+        int toff[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int k = 4 * grp + j;
+            toff[j] = k < 9 ? (k / 3) * CF0S + (k % 3) : -1;
+        }
+        const int vy0 = max(0, -Y1), vy1 = min(CF1H, im.h1 - Y1), vx0 = max(0, -X1), vx1 = min(CF1W, im.w1 - X1);
+        for (int t = wave; t < (CF1N + 15) / 16; t += 4) {
+            const int p = 16 * t + m;
+            const int r1 = p / CF1W, c1 = p - r1 * CF1W;
+            const int base = 2 * r1 * CF0S + 2 * c1;
+            i16x4 a;
+#pragma unroll
+            for (int j = 0; j < 4; j++) a[j] = (short)(p < CF1N && toff[j] >= 0 ? s_u[base + toff[j]] : 0);
+            const f32x4 acc = conv1_mfma(a, b);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int q = 16 * t + 4 * grp + r;
+                if (q < CF1N) {
+                    const int qy = q / CF1W, qx = q - qy * CF1W;
+                    const bool in = qy >= vy0 && qy < vy1 && qx >= vx0 && qx < vx1;
+                    s_a1[q * 16 + m] = in ? to_bf(fmaxf(acc[r] + bias, 0.0f)) : (uint16_t)0;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // C. conv2 (16 -> 32), K chunks = pairs of taps x 16 channels
+    {
+        uint4 w0[5], w1[5];
+#pragma unroll
+        for (int c = 0; c < 5; c++) {
+            const int t = 2 * c + (grp >> 1), ci0 = 8 * (grp & 1);
+            w0[c] = w1[c] = make_uint4(0, 0, 0, 0);
+            if (t < 9) {
+                w0[c] = *(const uint4 *)(wp2 + ((m * 9 + t) * 16 + ci0));
+                w1[c] = *(const uint4 *)(wp2 + (((m + 16) * 9 + t) * 16 + ci0));
+            }
+        }
+        const float bb0 = bf(prm[P_B2 + m]), bb1 = bf(prm[P_B2 + m + 16]);
+        const int vy0 = max(0, -Y2), vy1 = min(CF2H, im.h2 - Y2), vx0 = max(0, -X2), vx1 = min(CF2W, im.w2 - X2);
+        for (int t2 = wave; t2 < (CF2N + 15) / 16; t2 += 4) {
+            const int p = 16 * t2 + m;
+            const bool valid = p < CF2N;
+            const int r2 = valid ? p / CF2W : 0, c2 = valid ? p - r2 * CF2W : 0;
+            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < 5; c++) {
+                const int t = 2 * c + (grp >> 1), ci0 = 8 * (grp & 1);
+                uint4 av = make_uint4(0, 0, 0, 0);
+                if (t < 9 && valid) {
+                    const int q1 = (2 * r2 + t / 3) * CF1W + (2 * c2 + t % 3);
+                    av = *(const uint4 *)(s_a1 + q1 * 16 + ci0);
+                }
+                const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, w0[c]), acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, w1[c]), acc1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int q = 16 * t2 + 4 * grp + r;
+                if (q < CF2N) {
+                    const int qy = q / CF2W, qx = q - qy * CF2W;
+                    const bool in = qy >= vy0 && qy < vy1 && qx >= vx0 && qx < vx1;
+                    s_c2[q * 32 + m] = in ? to_bf(fmaxf(acc0[r] + bb0, 0.0f)) : (uint16_t)0;
+                    s_c2[q * 32 + m + 16] = in ? to_bf(fmaxf(acc1[r] + bb1, 0.0f)) : (uint16_t)0;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // D. conv3 (32 -> 32) + 1x1 head: waves 0 and 1 take tile rows 2w, 2w + 1
+    if (wave < CF3H / 2) {
+        const int r3 = 2 * wave + (m >> 3), c3 = m & 7;
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; t++) {
+            const int ci0 = 8 * grp;
+            const int q2 = (2 * r3 + t / 3) * CF2W + (2 * c3 + t % 3);
+            const uint4 av = *(const uint4 *)(s_c2 + q2 * 32 + ci0);
+            const uint4 b0 = *(const uint4 *)(wp3 + ((m * 9 + t) * 32 + ci0));
+            const uint4 b1 = *(const uint4 *)(wp3 + (((m + 16) * 9 + t) * 32 + ci0));
+            const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
+        }
+        const float bb0 = bf(prm[P_B3 + m]), bb1 = bf(prm[P_B3 + m + 16]);
+        const float hw0 = bf(prm[P_W4 + m]), hw1 = bf(prm[P_W4 + m + 16]);
+        float part[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const uint16_t v0 = to_bf(fmaxf(acc0[r] + bb0, 0.0f)), v1 = to_bf(fmaxf(acc1[r] + bb1, 0.0f));
+            part[r] = hw0 * bf(v0) + hw1 * bf(v1);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) part[r] += __shfl_xor(part[r], o);
+        }
+        if (m == 0) {
+            const float b4 = bf(prm[P_B4]);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int pr = 4 * grp + r;                 // pixel of this M tile
+                const int gy = Y3 + 2 * wave + (pr >> 3), gx = X3 + (pr & 7);
+                if (gy < im.h4 && gx < im.w4) z[im.px4 + (int64_t)gy * im.w4 + gx] = part[r] + b4;
             }
         }
     }
@@ -428,8 +634,9 @@ int32_t cnn_setup(vsfe_batch *b) {
     const int n = b->n_images;
     P->n = n;
     P->h_img.resize(n);
-    std::vector<int32_t> pre1(n + 1), pre2(n + 1), pre4(n + 1), pt2(n + 1), pt4(n + 1), pc(n + 1);
-    int64_t s1 = 0, s2 = 0, s4 = 0, st2 = 0, st4 = 0, sc = 0;
+    std::vector<int32_t> pre1(n + 1), pre2(n + 1), pre4(n + 1), pt2(n + 1), pt4(n + 1), pc(n + 1), pt1(n + 1),
+        ptf(n + 1);
+    int64_t s1 = 0, s2 = 0, s4 = 0, st2 = 0, st4 = 0, sc = 0, st1 = 0, stf = 0;
     for (int i = 0; i < n; i++) {
         const ImageDev &im = b->images[i];
         CnnImg &c = P->h_img[i];
@@ -454,6 +661,8 @@ int32_t cnn_setup(vsfe_batch *b) {
         pt2[i] = (int32_t)st2;
         pt4[i] = (int32_t)st4;
         pc[i] = (int32_t)sc;
+        pt1[i] = (int32_t)st1;
+        ptf[i] = (int32_t)stf;
         c.px1 = s1;
         c.px2 = s2;
         c.px4 = s4;
@@ -464,6 +673,8 @@ int32_t cnn_setup(vsfe_batch *b) {
         st2 += ((int64_t)c.w2 * c.h2 + 15) / 16;
         st4 += ((int64_t)c.w4 * c.h4 + 15) / 16;
         sc += (int64_t)c.ncx0 * c.ncy0;
+        st1 += ((int64_t)c.w1 * c.h1 + 15) / 16;
+        stf += (int64_t)((c.w4 + CF3W - 1) / CF3W) * ((c.h4 + CF3H - 1) / CF3H);
     }
     pre1[n] = (int32_t)s1;
     pre2[n] = (int32_t)s2;
@@ -471,13 +682,18 @@ int32_t cnn_setup(vsfe_batch *b) {
     pt2[n] = (int32_t)st2;
     pt4[n] = (int32_t)st4;
     pc[n] = (int32_t)sc;
+    pt1[n] = (int32_t)st1;
+    ptf[n] = (int32_t)stf;
     P->px1 = s1;
     P->px2 = s2;
     P->px4 = s4;
     P->t2 = st2;
     P->t4 = st4;
     P->cells = sc;
-    for (auto *v : {&pre1, &pre2, &pre4, &pt2, &pt4, &pc}) P->h_pre.insert(P->h_pre.end(), v->begin(), v->end());
+    P->t1 = st1;
+    P->tf = stf;
+    for (auto *v : {&pre1, &pre2, &pre4, &pt2, &pt4, &pc, &pt1, &ptf})
+        P->h_pre.insert(P->h_pre.end(), v->begin(), v->end());
     int64_t at = 0;
     P->off_wp2 = at;
     at = align256(at + 32 * 9 * 16 * 2);
@@ -543,9 +759,9 @@ static int32_t run_forward(const vsfe_batch *b, const CnnPlan *P, const uint8_t 
     uint16_t *wp2 = (uint16_t *)(ws + P->off_wp2), *wp3 = (uint16_t *)(ws + P->off_wp3);
     uint16_t *a1 = (uint16_t *)(ws + P->off_a1), *a2 = (uint16_t *)(ws + P->off_a2), *a3 = (uint16_t *)(ws + P->off_a3);
     hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, prm, wp2, wp3);
-    if (P->px1 > 0)
-        hipLaunchKernelGGL(cnn_conv1_kernel, dim3((unsigned)((P->px1 + 255) / 256)), dim3(256), 0, st, P->d_img, pre, n,
-                           P->px1, pyr, prm, a1);
+    if (P->t1 > 0)
+        hipLaunchKernelGGL(cnn_conv1_kernel, dim3((unsigned)((P->t1 + 3) / 4)), dim3(256), 0, st, P->d_img,
+                           pre + 6 * (n + 1), n, P->t1, pyr, prm, a1);
     if (P->t2 > 0)
         hipLaunchKernelGGL((cnn_conv_mfma_kernel<16, false>), dim3((unsigned)((P->t2 + 3) / 4)), dim3(256), 0, st,
                            P->d_img, pre + 3 * (n + 1), n, P->t2, a1, a2, wp2, prm, (float *)nullptr);
@@ -586,7 +802,13 @@ int32_t cnn_propose(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *pyr
     if (rc) return rc;
     if (!pyr || !params_bf16 || !workspace || !grid_logits || !cell_mask) return fail(VSFE_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
-    rc = run_forward(b, P, pyr, params_bf16, (uint8_t *)workspace, grid_logits, st);
+    uint8_t *ws = (uint8_t *)workspace;
+    uint16_t *wp2 = (uint16_t *)(ws + P->off_wp2), *wp3 = (uint16_t *)(ws + P->off_wp3);
+    hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, params_bf16, wp2, wp3);
+    if (P->tf > 0)
+        hipLaunchKernelGGL(cnn_fused_fwd_kernel, dim3((unsigned)P->tf), dim3(256), 0, st, P->d_img,
+                           P->d_pre + 7 * (P->n + 1), P->n, pyr, params_bf16, wp2, wp3, grid_logits);
+    rc = check_launch("cnn_propose (forward)");
     if (rc) return rc;
     if (P->cells > 0)
         hipLaunchKernelGGL(cnn_cells_kernel, dim3((unsigned)((P->cells + 255) / 256)), dim3(256), 0, st, P->d_img,

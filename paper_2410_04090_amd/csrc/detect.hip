@@ -24,8 +24,10 @@
 //     pixels (0, 4, 8, 12), i.e. one of {0, 8} and one of {4, 12}, so a
 //     bright run needs min(max(p0, p8), max(p4, p12)) > c + eps (dark:
 //     max(min(p0, p8), min(p4, p12)) < c - eps), at the weaker threshold.
-//  3. Candidates go to per-wave LDS queues (ballot prefix), so the full ring
-//     test runs densely over candidates only: masks are built with alignbit
+//  3. Each lane collects its candidates in a bit mask over its rows; one
+//     wave prefix sum of the counts places them in a per-wave LDS queue, so
+//     the full ring test runs densely over candidates only (the screen
+//     re-derives the polarity from the same compass test): masks are built with alignbit
 //     (one op inserts one sign bit; run lengths do not depend on bit order)
 //     and runs are tested by shift-and doubling.
 //  4. Keys reduce per cell with LDS atomicMax (order independent, so the
@@ -42,7 +44,7 @@ constexpr int FT_W = 100;
 constexpr int FT_MAX_ROWS = 32;
 constexpr int FT_ROWS = FT_MAX_ROWS + 6;
 constexpr int FT_MAX_CELLS = 512;
-constexpr int FT_QSEG = (FT_MAX_ROWS / 4) * 2 * FT_HALF + FT_HALF;   // + one dummy slot per lane
+constexpr int FT_Q1 = FT_MAX_ROWS * 2 * FT_HALF;   // candidate queue (every tile pixel)
 constexpr int FT_Q2 = 2048;                      // second-stage queue (overflow handled inline)
 
 struct DetParams {
@@ -54,9 +56,10 @@ typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ us2 as_us2(uint32_t v) { return __builtin_bit_cast(us2, v); }
 __device__ __forceinline__ uint32_t as_u32(us2 v) { return __builtin_bit_cast(uint32_t, v); }
 
-// ring offsets (dx, dy) in cyclic order
-__constant__ int8_t c_ring_dx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
-__constant__ int8_t c_ring_dy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+// ring offsets (dx, dy) in cyclic order (compile-time, so that every ring
+// read is one LDS access with an immediate offset)
+constexpr int kRingDx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+constexpr int kRingDy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
 
 // Does the 16-bit mask hold a cyclic run of >= k ones (1 <= k <= 16)?  The
 // mask is doubled to 32 bits so cyclic runs are contiguous; r_p marks starts
@@ -104,13 +107,30 @@ __device__ __forceinline__ bool cell_runs(const uint8_t *mask0, const LevelDev &
     const int64_t S = lv.scale_q16, c = lv.cell, c0 = l0.cell;
     const int64_t fx0 = ((int64_t)cx * c * S) >> 16, fx1 = (((int64_t)cx * c + c) * S + 65535) >> 16;
     const int64_t fy0 = ((int64_t)cy * c * S) >> 16, fy1 = (((int64_t)cy * c + c) * S + 65535) >> 16;
-    int a0 = (int)(fx0 / c0), a1 = (int)((fx1 - 1) / c0), b0 = (int)(fy0 / c0), b1 = (int)((fy1 - 1) / c0);
+    // footprints lie inside the level-0 image, so 32-bit divisions suffice
+    const int ic0 = (int)c0;
+    int a0 = (int)fx0 / ic0, a1 = (int)(fx1 - 1) / ic0, b0 = (int)fy0 / ic0, b1 = (int)(fy1 - 1) / ic0;
     a1 = a1 < l0.ncx - 1 ? a1 : l0.ncx - 1;
     b1 = b1 < l0.ncy - 1 ? b1 : l0.ncy - 1;
     for (int y = b0; y <= b1; y++)
         for (int x = a0; x <= a1; x++)
             if (mask0[y * l0.ncx + x]) return true;
     return false;
+}
+
+// Expand the level-0 cell mask to run flags of every cell of every level
+// (one thread per cell), so the detector reads one byte per cell.
+__global__ __launch_bounds__(256) void expand_mask_kernel(const ImageDev *__restrict__ imgs,
+                                                          const CellChunk *__restrict__ chunks,
+                                                          const uint8_t *__restrict__ mask0,
+                                                          uint8_t *__restrict__ run) {
+    const CellChunk ch = chunks[blockIdx.x];
+    const ImageDev &im = imgs[ch.image];
+    const LevelDev lv = im.lv[ch.level];
+    const int idx = (int)ch.first + (int)threadIdx.x;
+    if (idx >= lv.ncx * lv.ncy) return;
+    const int cy = idx / lv.ncx, cx = idx - cy * lv.ncx;
+    run[lv.cell_offset + idx] = cell_runs(mask0 + im.cell0_offset, im.lv[0], lv, cx, cy) ? 1 : 0;
 }
 
 // 16 consecutive bytes of a row starting at x (zero outside [0, w)).
@@ -144,7 +164,7 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
                                                       uint32_t *__restrict__ cell_keys,
                                                       uint16_t *__restrict__ crf, DetParams prm) {
     __shared__ __attribute__((aligned(16))) uint32_t tile[FT_ROWS * FT_W];
-    __shared__ uint16_t s_q[4 * FT_QSEG];
+    __shared__ uint16_t s_q[FT_Q1];
     __shared__ uint16_t s_q2[FT_Q2];
     __shared__ uint32_t s_hi[FT_MAX_CELLS], s_lo[FT_MAX_CELLS];
     __shared__ uint8_t s_run[FT_MAX_CELLS];
@@ -169,7 +189,7 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
     __syncthreads();
     for (int k = tid; k < nk; k += 256) {
         bool run = true;
-        if (mask) run = cell_runs(mask + im.cell0_offset, im.lv[0], lv, it.cx0 + k % it.nkx, it.cy0 + k / it.nkx);
+        if (mask) run = mask[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] != 0;
         s_run[k] = run;
         s_hi[k] = 0;
         s_lo[k] = 0;
@@ -211,21 +231,24 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
     }
     __syncthreads();
 
-    // 2. prefilter, 3a. per-wave candidate queues
-    //    entry = dark << 14 | bright << 13 | row << 7 | column
+    // 2. prefilter: each lane collects its candidates (rows wave + 4k) in a
+    //    bit mask: bit k = column lane, bit 16 + k = column lane + 64.
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int B = prm.border;
     const int gxl = x0 + lane, gxh = x0 + FT_HALF + lane;
     const bool okl = lane < tw && gxl >= B && gxl < lv.w - B;
     const bool okh = FT_HALF + lane < tw && gxh >= B && gxh < lv.w - B;
-    const uint32_t vmask = (okl ? 0xFFFFu : 0u) | (okh ? 0xFFFF0000u : 0u);
     const us2 e2 = {(unsigned short)prm.eps_min, (unsigned short)prm.eps_min};
-    uint16_t *q = s_q + wave * FT_QSEG;
-    const int dummy = FT_QSEG - FT_HALF + lane;
-    int qn = 0;
+    const us2 one2 = {1, 1};
     const int ylo = max(B - y0, 0), yhi = min(lv.h - B - y0, th);
-    for (int r = wave + ((ylo - wave + 3) & ~3); r < yhi; r += 4) {
+    const int kxl = lane / c, kxh = (FT_HALF + lane) / c;
+    uint32_t cm = 0;
+#pragma unroll
+    for (int k = 0; k < FT_MAX_ROWS / 4; k++) {
+        const int r = wv + 4 * k;
+        if (r < ylo || r >= yhi) continue;        // uniform
         const uint32_t *t = &tile[(r + 3) * FT_W + lane + 3 + delta];
-        uint32_t tbu = vmask, tdu = vmask;
+        uint32_t cand = 0xFFFFFFFFu;
         if (PF) {
             const us2 C = as_us2(t[0]);
             const us2 P0 = as_us2(t[-3 * FT_W]), P8 = as_us2(t[3 * FT_W]);
@@ -238,21 +261,50 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
                 Mb = __builtin_elementwise_max(__builtin_elementwise_max(P0, P8), __builtin_elementwise_max(P4, P12));
                 Md = __builtin_elementwise_min(__builtin_elementwise_min(P0, P8), __builtin_elementwise_min(P4, P12));
             }
-            tbu &= as_u32(__builtin_elementwise_sub_sat(Mb, C + e2));
-            tdu &= as_u32(__builtin_elementwise_sub_sat(__builtin_elementwise_sub_sat(C, e2), Md));
+            cand = as_u32(__builtin_elementwise_sub_sat(Mb, C + e2)) |
+                   as_u32(__builtin_elementwise_sub_sat(__builtin_elementwise_sub_sat(C, e2), Md));
         }
-        const uint32_t pol_l = ((tbu & 0xFFFFu) ? (1u << 13) : 0u) | ((tdu & 0xFFFFu) ? (1u << 14) : 0u);
-        const uint32_t pol_h = ((tbu >> 16) ? (1u << 13) : 0u) | ((tdu >> 16) ? (1u << 14) : 0u);
-        const bool cl = pol_l != 0, ch = pol_h != 0;
-        const uint64_t bl = __ballot(cl), bh = __ballot(ch);
-        const int nl = __popcll(bl);
-        const int pl = __builtin_amdgcn_mbcnt_hi((uint32_t)(bl >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bl, 0));
-        const int ph = __builtin_amdgcn_mbcnt_hi((uint32_t)(bh >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bh, 0));
-        q[cl ? qn + pl : dummy] = (uint16_t)(pol_l | (r << 7) | lane);
-        q[ch ? qn + nl + ph : dummy] = (uint16_t)(pol_h | (r << 7) | (FT_HALF + lane));
-        qn += nl + __popcll(bh);
+        // (low != 0, high != 0) as two 16-bit flags in one v_pk_min_u16 (in asm:
+        // the compiler would otherwise expand it into compares and selects)
+        uint32_t f;
+        asm volatile("v_pk_min_u16 %0, %1, %2" : "=v"(f) : "v"(cand), "v"(as_u32(one2)));
+        cm |= f << k;
     }
-    if (lane == 0) s_qcnt[wave] = qn;
+    cm &= (okl ? 0xFFu : 0u) | (okh ? 0xFF0000u : 0u);
+    if (mask && cm) {
+        // learned gating: pixels of skipped cells never become candidates
+        uint32_t gm = 0;
+#pragma unroll
+        for (int k = 0; k < FT_MAX_ROWS / 4; k++) {
+            const int r = wv + 4 * k;
+            if (r >= th) break;                          // uniform
+            const int kb = (r / c) * it.nkx;
+            gm |= (s_run[kb + min(kxl, it.nkx - 1)] ? 1u : 0u) << k;
+            gm |= (s_run[kb + min(kxh, it.nkx - 1)] ? 0x10000u : 0u) << k;
+        }
+        cm &= gm;
+    }
+
+    // 3a. candidate queue (entry = row << 7 | column), contiguous over the
+    //     block: a wave scan of the per-lane counts, the waves' totals, then
+    //     every lane writes its own entries
+    const int cnt = __popc(cm);
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    if (lane == 63) s_qcnt[wv] = incl;
+    __syncthreads();
+    const int q0 = s_qcnt[0], q1 = s_qcnt[1], q2 = s_qcnt[2], q3 = s_qcnt[3];
+    const int total = q0 + q1 + q2 + q3;
+    int pos = incl - cnt + (wv > 0 ? q0 : 0) + (wv > 1 ? q1 : 0) + (wv > 2 ? q2 : 0);
+    while (cm) {
+        const int bit = __builtin_ctz(cm);
+        cm &= cm - 1;
+        s_q[pos++] = (uint16_t)(((wv + 4 * (bit & 15)) << 7) | (lane + FT_HALF * (bit >> 4)));
+    }
     __syncthreads();
 
     const uint16_t *t16 = (const uint16_t *)tile;
@@ -260,22 +312,24 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
     auto load_ring = [&](int r, int col, int *p) {
         const uint16_t *win = t16 + 2 * (r * FT_W + (col & 63) + delta) + (col >> 6);
 #pragma unroll
-        for (int j = 0; j < 16; j++) p[j] = win[2 * ((c_ring_dy[j] + 3) * FT_W + c_ring_dx[j] + 3)];
+        for (int j = 0; j < 16; j++) p[j] = win[2 * ((kRingDy[j] + 3) * FT_W + kRingDx[j] + 3)];
         return (int)win[2 * (3 * FT_W + 3)];
     };
     // decision for a screened pixel: rb / rd = polarities with a run >= p_min at eps_min
-    auto finish = [&](int r, int col, bool rb, bool rd) {
+    // with p_min = 9 the screen, which runs at eps_min (eps_lo if there is a
+    // fallback threshold, else eps_hi), has already taken the corner decision
+    // at that threshold (cmin)
+    auto finish = [&](int r, int col, bool rb, bool rd, bool cmin) {
         int p[16];
         const int ctr = load_ring(r, col, p);
         bool c_hi = false, c_lo = false;
         if constexpr (P9) {
             // p_min = 9: a bright and a dark run cannot coexist, one polarity decides
-            const bool dk = !rb;
             if (LO) {
-                c_lo = br_corner<true>(ring_mask(p, ctr, prm.eps_lo, dk), 9, 13);
-                c_hi = br_corner<true>(ring_mask(p, ctr, prm.eps_hi, dk), 9, 13);
+                c_lo = cmin;
+                c_hi = br_corner<true>(ring_mask(p, ctr, prm.eps_hi, !rb), 9, 13);
             } else {
-                c_hi = br_corner<true>(ring_mask(p, ctr, prm.eps_hi, dk), 9, 13);
+                c_hi = cmin;
             }
         } else {
             if (LO) {
@@ -286,9 +340,12 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
             if (rd) c_hi = c_hi || br_corner<false>(ring_mask(p, ctr, prm.eps_hi, true), prm.p_min, prm.p_max);
         }
         if (!c_hi && !c_lo) return;
-        int score = 0;
+        // response: sum of |I_p - I_c| over the ring, two pixels per v_sad_u16
+        const uint32_t c2 = (uint32_t)ctr * 0x10001u;
+        uint32_t score = 0;
 #pragma unroll
-        for (int j = 0; j < 16; j++) score += abs(p[j] - ctr);
+        for (int j = 0; j < 16; j += 2)
+            score = __builtin_amdgcn_sad_u16((uint32_t)p[j] | ((uint32_t)p[j + 1] << 16), c2, score);
         if (crf && c_hi) crf[lv.crf_offset + (int64_t)(y0 + r) * lv.w + (x0 + col)] = (uint16_t)score;
         const int kx = col / c, ky = r / c;
         const int k = ky * it.nkx + kx;
@@ -302,22 +359,37 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
 
     // 3b. screen every candidate densely: a run >= p_min at the weaker
     //     threshold is necessary for a corner at either threshold.  Survivors
-    //     (entry = rd << 13 | rb << 12 | row << 7 | column) go to a second queue.
-    const int n0 = s_qcnt[0], n1 = n0 + s_qcnt[1], n2 = n1 + s_qcnt[2], total = n2 + s_qcnt[3];
+    //     (entry = cmin << 14 | rd << 13 | rb << 12 | row << 7 | column) go to
+    //     a second queue.
     for (int i = tid; i < total; i += 256) {
-        const int w = (i >= n0) + (i >= n1) + (i >= n2);
-        const int base = w == 0 ? 0 : (w == 1 ? n0 : (w == 2 ? n1 : n2));
-        const int e = s_q[w * FT_QSEG + (i - base)];
+        const int e = s_q[i];
         const int r = (e >> 7) & 63, col = e & 127;
-        const bool pb = (e >> 13) & 1, pd = (e >> 14) & 1;
         int p[16];
         const int ctr = load_ring(r, col, p);
-        bool rb = false, rd = false;
+        // polarities that passed the prefilter (the same compass test)
+        bool pb = true, pd = true;
+        if (PF == 2) {
+            pb = min(max(p[0], p[8]), max(p[4], p[12])) > ctr + prm.eps_min;
+            pd = max(min(p[0], p[8]), min(p[4], p[12])) < ctr - prm.eps_min;
+        } else if (PF == 1) {
+            pb = max(max(p[0], p[8]), max(p[4], p[12])) > ctr + prm.eps_min;
+            pd = min(min(p[0], p[8]), min(p[4], p[12])) < ctr - prm.eps_min;
+        }
+        bool rb = false, rd = false, cmin = false;
         if constexpr (P9) {
-            rb = pb && run_ge<true>(ring_mask(p, ctr, prm.eps_min, false), 9);
-            // both polarities passed the compass test (rare): try dark only if bright failed
-            const bool try_d = pd && !rb;
-            if (try_d) rd = run_ge<true>(ring_mask(p, ctr, prm.eps_min, true), 9);
+            // one polarity per lane (bright if it passed, else dark), so the
+            // wave does not run both; the other one only if both passed (rare)
+            bool dk = !pb;
+            uint32_t m = ring_mask(p, ctr, prm.eps_min, dk);
+            bool run = run_ge<true>(m, 9);
+            if (!run && pb && pd) {
+                dk = true;
+                m = ring_mask(p, ctr, prm.eps_min, true);
+                run = run_ge<true>(m, 9);
+            }
+            rb = run && !dk;
+            rd = run && dk;
+            cmin = run && !run_ge<false>(m, 14);
         } else {
             if (pb) rb = run_ge<false>(ring_mask(p, ctr, prm.eps_min, false), prm.p_min);
             if (pd) rd = run_ge<false>(ring_mask(p, ctr, prm.eps_min, true), prm.p_min);
@@ -328,10 +400,12 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
             int wbase = 0;
             if (lane == __builtin_ffsll((long long)bal) - 1) wbase = atomicAdd(&s_n2, __popcll(bal));
             wbase = __shfl(wbase, __builtin_ffsll((long long)bal) - 1);
-            const int pos = wbase + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+            const int pos2 = wbase + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
             if (surv) {
-                if (pos < FT_Q2) s_q2[pos] = (uint16_t)((rd ? 1 << 13 : 0) | (rb ? 1 << 12 : 0) | (r << 7) | col);
-                else finish(r, col, rb, rd);       // queue full: decide in place
+                if (pos2 < FT_Q2)
+                    s_q2[pos2] = (uint16_t)((cmin ? 1 << 14 : 0) | (rd ? 1 << 13 : 0) | (rb ? 1 << 12 : 0) | (r << 7) | col);
+                else
+                    finish(r, col, rb, rd, cmin);      // queue full: decide in place
             }
         }
     }
@@ -340,7 +414,7 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
     const int ns = min(s_n2, FT_Q2);
     for (int i = tid; i < ns; i += 256) {
         const int e = s_q2[i];
-        finish((e >> 7) & 31, e & 127, (e >> 12) & 1, (e >> 13) & 1);
+        finish((e >> 7) & 31, e & 127, (e >> 12) & 1, (e >> 13) & 1, (e >> 14) & 1);
     }
     __syncthreads();
     for (int k = tid; k < nk; k += 256) {
@@ -357,14 +431,39 @@ __global__ void fill_u16_kernel(uint16_t *p, int64_t n) {
 }
 
 template <int PF, bool LO>
-static void launch_fast(const vsfe_batch *b, hipStream_t st, const uint8_t *images, const uint8_t *pyr,
-                        const uint8_t *mask, uint32_t *keys, uint16_t *crf, const DetParams &prm) {
+static void launch_fast(const vsfe_batch *b, const DetItem *items, int32_t n_items, hipStream_t st,
+                        const uint8_t *images, const uint8_t *pyr, const uint8_t *mask, uint32_t *keys,
+                        uint16_t *crf, const DetParams &prm) {
     if (prm.p_min == 9 && prm.p_max == 13)
-        hipLaunchKernelGGL((fast_br_kernel<PF, LO, true>), dim3(b->n_det_items), dim3(256), 0, st, b->d_images,
-                           b->d_det_items, images, pyr, mask, keys, crf, prm);
+        hipLaunchKernelGGL((fast_br_kernel<PF, LO, true>), dim3(n_items), dim3(256), 0, st, b->d_images, items,
+                           images, pyr, mask, keys, crf, prm);
     else
-        hipLaunchKernelGGL((fast_br_kernel<PF, LO, false>), dim3(b->n_det_items), dim3(256), 0, st, b->d_images,
-                           b->d_det_items, images, pyr, mask, keys, crf, prm);
+        hipLaunchKernelGGL((fast_br_kernel<PF, LO, false>), dim3(n_items), dim3(256), 0, st, b->d_images, items,
+                           images, pyr, mask, keys, crf, prm);
+}
+
+int32_t detect_launch(const vsfe_ctx *ctx, const vsfe_batch *b, const DetItem *items, int32_t n_items,
+                      const uint8_t *images, const uint8_t *pyr, const uint8_t *cell_mask, uint32_t *cell_keys,
+                      uint16_t *crf_debug, hipStream_t st) {
+    const vsfe_params &p = ctx->p;
+    DetParams prm;
+    prm.eps_hi = p.eps_hi;
+    prm.eps_lo = p.eps_lo;
+    prm.p_min = p.p_min;
+    prm.p_max = p.p_max;
+    prm.border = p.border;
+    prm.eps_min = p.eps_lo >= 0 ? p.eps_lo : p.eps_hi;
+    prm.aligned = b->aligned_input16 && (((uintptr_t)images & 15) == 0) ? 1 : 0;
+    const int pf = p.p_min >= 9 ? 2 : (p.p_min >= 5 ? 1 : 0);
+    const bool lo = p.eps_lo >= 0;
+    if (n_items <= 0) return VSFE_OK;
+    if (pf == 2 && lo) launch_fast<2, true>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
+    else if (pf == 2) launch_fast<2, false>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
+    else if (pf == 1 && lo) launch_fast<1, true>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
+    else if (pf == 1) launch_fast<1, false>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
+    else if (lo) launch_fast<0, true>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
+    else launch_fast<0, false>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
+    return check_launch("fast_br_detect");
 }
 
 }  // namespace vsfe
@@ -377,29 +476,22 @@ extern "C" int32_t fast_br_detect(const vsfe_ctx *ctx, const vsfe_batch *b, cons
     int32_t rc = check_common(ctx, b, status);
     if (rc) return rc;
     if (!images || !cell_keys || (!pyr && b->info.n_levels > 1)) return fail(VSFE_EINVAL, "null buffer");
-    const vsfe_params &p = ctx->p;
-    DetParams prm;
-    prm.eps_hi = p.eps_hi;
-    prm.eps_lo = p.eps_lo;
-    prm.p_min = p.p_min;
-    prm.p_max = p.p_max;
-    prm.border = p.border;
-    prm.eps_min = p.eps_lo >= 0 ? p.eps_lo : p.eps_hi;
-    prm.aligned = b->aligned_input16 && (((uintptr_t)images & 15) == 0) ? 1 : 0;
-    const int pf = p.p_min >= 9 ? 2 : (p.p_min >= 5 ? 1 : 0);
-    const bool lo = p.eps_lo >= 0;
     hipStream_t st = (hipStream_t)stream;
     if (crf_debug && b->info.crf_elems > 0) {
         hipLaunchKernelGGL(fill_u16_kernel, dim3(1024), dim3(256), 0, st, crf_debug, (int64_t)b->info.crf_elems);
         rc = check_launch("fast_br_detect (response dump fill)");
         if (rc) return rc;
     }
-    if (b->n_det_items <= 0) return VSFE_OK;
-    if (pf == 2 && lo) launch_fast<2, true>(b, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    else if (pf == 2) launch_fast<2, false>(b, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    else if (pf == 1 && lo) launch_fast<1, true>(b, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    else if (pf == 1) launch_fast<1, false>(b, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    else if (lo) launch_fast<0, true>(b, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    else launch_fast<0, false>(b, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    return check_launch("fast_br_detect");
+    const uint8_t *run = nullptr;
+    if (cell_mask) {
+        if (!b->d_run) return fail(VSFE_EINVAL, "batch has no run-flag table");
+        if (b->n_chunks > 0) {
+            hipLaunchKernelGGL(expand_mask_kernel, dim3(b->n_chunks), dim3(PYCA_CHUNK), 0, st, b->d_images,
+                               b->d_chunks, cell_mask, b->d_run);
+            rc = check_launch("fast_br_detect (mask expansion)");
+            if (rc) return rc;
+        }
+        run = b->d_run;
+    }
+    return detect_launch(ctx, b, b->d_det_items, b->n_det_items, images, pyr, run, cell_keys, crf_debug, st);
 }

@@ -1,0 +1,188 @@
+// Detector tile planning and the batch autotuner.
+//
+// The detector takes one rectangle of whole cells per 256-thread block.  A
+// tile shape trades halo overhead (6 extra rows and columns per tile) and
+// per-block fixed cost against the number of blocks in flight, and the best
+// trade differs per pyramid level because the cell side shrinks from 32 to 8
+// pixels.  The autotuner times every distinct whole-cell shape that fits the
+// detector's 128 x 32 pixel tile on the batch's own data, level by level,
+// and keeps the fastest.  Results never depend on the shape: cells are
+// reduced inside one block.
+#include <string.h>
+
+#include <algorithm>
+
+#include "vsfe_internal.h"
+
+namespace vsfe {
+
+static void cells_per_tile(int tile_w, int tile_h, int cell, int *nkx, int *nky) {
+    *nkx = std::min(32, std::max(1, tile_w / cell));
+    *nky = std::min(16, std::max(1, tile_h / cell));
+}
+
+void det_items_level(const vsfe_batch *b, int level, int tile_w, int tile_h, std::vector<DetItem> *out) {
+    for (int i = 0; i < b->n_images; i++) {
+        const LevelDev &lv = b->images[i].lv[level];
+        int nkx, nky;
+        cells_per_tile(tile_w, tile_h, lv.cell, &nkx, &nky);
+        for (int cy = 0; cy < lv.ncy; cy += nky)
+            for (int cx = 0; cx < lv.ncx; cx += nkx)
+                out->push_back(DetItem{(uint16_t)i, (uint16_t)level, (uint16_t)cx, (uint16_t)cy,
+                                       (uint16_t)std::min(nkx, lv.ncx - cx), (uint16_t)std::min(nky, lv.ncy - cy),
+                                       0, 0});
+    }
+}
+
+void det_items_build(vsfe_batch *b) {
+    const int L = b->info.n_levels;
+    b->h_det_items.clear();
+    b->det_start.assign(L + 1, 0);
+    for (int l = 0; l < L; l++) {
+        b->det_start[l] = (int32_t)b->h_det_items.size();
+        det_items_level(b, l, b->tile_w[l], b->tile_h[l], &b->h_det_items);
+    }
+    b->det_start[L] = (int32_t)b->h_det_items.size();
+    b->n_det_items = (int32_t)b->h_det_items.size();
+}
+
+static bool tile_ok(int tw, int th) { return tw >= 8 && tw <= 128 && th >= 8 && th <= 32; }
+
+static int32_t upload_items(const std::vector<DetItem> &v, DetItem **dst) {
+    *dst = nullptr;
+    if (v.empty()) return VSFE_OK;
+    if (hipMalloc((void **)dst, v.size() * sizeof(DetItem)) != hipSuccess)
+        return fail(VSFE_EHIP, "hipMalloc of detector items failed");
+    if (hipMemcpy(*dst, v.data(), v.size() * sizeof(DetItem), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(VSFE_EHIP, "upload of detector items failed");
+    return VSFE_OK;
+}
+
+// Replace the device item table after b->tile_w / b->tile_h changed.
+static int32_t det_items_refresh(vsfe_batch *b) {
+    det_items_build(b);
+    DetItem *d = nullptr;
+    int32_t rc = upload_items(b->h_det_items, &d);
+    if (rc) return rc;
+    if (b->d_det_items) (void)hipFree(b->d_det_items);
+    b->d_det_items = d;
+    return VSFE_OK;
+}
+
+}  // namespace vsfe
+
+using namespace vsfe;
+
+extern "C" {
+
+int32_t vsfe_batch_tiles_get(const vsfe_batch *b, int32_t *tile_w, int32_t *tile_h) {
+    if (!b || !tile_w || !tile_h) return fail(VSFE_EINVAL, "null argument");
+    for (int l = 0; l < b->info.n_levels; l++) {
+        tile_w[l] = b->tile_w[l];
+        tile_h[l] = b->tile_h[l];
+    }
+    return VSFE_OK;
+}
+
+int32_t vsfe_batch_set_tiles(vsfe_batch *b, const int32_t *tile_w, const int32_t *tile_h) {
+    if (!b || !tile_w || !tile_h) return fail(VSFE_EINVAL, "null argument");
+    for (int l = 0; l < b->info.n_levels; l++)
+        if (!tile_ok(tile_w[l], tile_h[l])) return fail(VSFE_EINVAL, "tile out of range at level " + std::to_string(l));
+    if (hipDeviceSynchronize() != hipSuccess) return fail(VSFE_EHIP, "device synchronisation failed");
+    for (int l = 0; l < b->info.n_levels; l++) {
+        b->tile_w[l] = tile_w[l];
+        b->tile_h[l] = tile_h[l];
+    }
+    return det_items_refresh(b);
+}
+
+int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *images, const uint8_t *pyr,
+                            uint32_t *cell_keys, int32_t *status, int32_t reps, void *stream,
+                            vsfe_tune_report *out) {
+    int32_t rc = check_common(ctx, b, status);
+    if (rc) return rc;
+    if (!images || !cell_keys || !out || (!pyr && b->info.n_levels > 1)) return fail(VSFE_EINVAL, "null argument");
+    if (reps < 1 || reps > 1000) return fail(VSFE_EINVAL, "reps must be in 1..1000");
+    hipStream_t st = (hipStream_t)stream;
+    const int L = b->info.n_levels;
+    memset(out, 0, sizeof(*out));
+    out->n_levels = L;
+    static const int kW[] = {16, 24, 32, 40, 48, 64, 80, 96, 112, 128};
+    static const int kH[] = {8, 12, 16, 24, 32};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(VSFE_EHIP, "hipEventCreate failed");
+    DetItem *d_items = nullptr;
+    size_t cap = 0;
+    for (int l = 0; l < L && !rc; l++) {
+        const int c = b->images[0].lv[l].cell;
+        // candidate shapes: distinct (cells across, cells down); the batch's
+        // current shape first so that its time is reported as the baseline
+        std::vector<std::pair<int, int>> cand{{b->tile_w[l], b->tile_h[l]}};
+        std::vector<std::pair<int, int>> seen;
+        int nx0, ny0;
+        cells_per_tile(b->tile_w[l], b->tile_h[l], c, &nx0, &ny0);
+        seen.push_back({nx0, ny0});
+        for (int tw : kW)
+            for (int th : kH) {
+                int nx, ny;
+                cells_per_tile(tw, th, c, &nx, &ny);
+                if (std::find(seen.begin(), seen.end(), std::make_pair(nx, ny)) != seen.end()) continue;
+                seen.push_back({nx, ny});
+                cand.push_back({tw, th});
+            }
+        float best = 0.f;
+        int best_k = 0;
+        for (size_t k = 0; k < cand.size() && !rc; k++) {
+            std::vector<DetItem> items;
+            det_items_level(b, l, cand[k].first, cand[k].second, &items);
+            if (items.size() > cap) {
+                if (d_items) (void)hipFree(d_items);
+                d_items = nullptr;
+                if (hipMalloc((void **)&d_items, items.size() * sizeof(DetItem)) != hipSuccess) {
+                    rc = fail(VSFE_EHIP, "hipMalloc of tuning items failed");
+                    break;
+                }
+                cap = items.size();
+            }
+            if (hipMemcpy(d_items, items.data(), items.size() * sizeof(DetItem), hipMemcpyHostToDevice) != hipSuccess) {
+                rc = fail(VSFE_EHIP, "upload of tuning items failed");
+                break;
+            }
+            const int n = (int)items.size();
+            rc = detect_launch(ctx, b, d_items, n, images, pyr, nullptr, cell_keys, nullptr, st);   // warm-up
+            if (rc) break;
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < reps && !rc; r++)
+                rc = detect_launch(ctx, b, d_items, n, images, pyr, nullptr, cell_keys, nullptr, st);
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) rc = fail(VSFE_EHIP, "tuning run failed");
+            if (rc) break;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const float us = ms * 1000.f / reps;
+            if (k == 0) out->us_before[l] = us;
+            if (k == 0 || us < best) {
+                best = us;
+                best_k = (int)k;
+            }
+        }
+        int nx, ny;
+        cells_per_tile(cand[best_k].first, cand[best_k].second, c, &nx, &ny);
+        // store the extent actually used (whole cells) so that every image of
+        // the batch gets the same cell counts
+        b->tile_w[l] = std::min(128, std::max(8, nx * c));
+        b->tile_h[l] = std::min(32, std::max(8, ny * c));
+        out->tile_w[l] = nx * c;
+        out->tile_h[l] = ny * c;
+        out->us[l] = best;
+        out->n_tried[l] = (int32_t)cand.size();
+    }
+    if (d_items) (void)hipFree(d_items);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    return det_items_refresh(b);
+}
+
+}  // extern "C"

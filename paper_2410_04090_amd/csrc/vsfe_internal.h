@@ -88,12 +88,17 @@ struct vsfe_batch {
     uint32_t *d_coord = nullptr;
     bool aligned_input = true;                   // level-0 rows start on 4-byte boundaries
     bool aligned_input16 = true;                 // ... and on 16-byte boundaries
+    // detector work: per-level tile extents (pixels), items level-major,
+    // items of level l are [det_start[l], det_start[l+1])
+    int32_t tile_w[VSFE_MAX_LEVELS] = {}, tile_h[VSFE_MAX_LEVELS] = {};
+    std::vector<int32_t> det_start;
     int32_t n_det_items = 0;
     std::vector<vsfe::DetItem> h_det_items;
     vsfe::DetItem *d_det_items = nullptr;
     int32_t n_chunks = 0;
     std::vector<vsfe::CellChunk> h_chunks;
     vsfe::CellChunk *d_chunks = nullptr;
+    uint8_t *d_run = nullptr;                    // per-cell run flags of the gated detector
     bool pairs_ok = false;                       // even count, equal pair sizes
     void *cnn = nullptr;                         // proposer plan (levels >= 4)
     vsfe_cnn_info info_cnn{};
@@ -109,6 +114,15 @@ int32_t check_common(const vsfe_ctx *ctx, const vsfe_batch *b, int32_t *status);
 // proposer geometry of a batch (no-op below 4 levels) and its release
 int32_t cnn_setup(vsfe_batch *b);
 void cnn_release(vsfe_batch *b);
+
+// detector tiles of one level for a target extent (whole cells, at least one)
+void det_items_level(const vsfe_batch *b, int level, int tile_w, int tile_h, std::vector<DetItem> *out);
+// rebuild every level's detector items from b->tile_w / b->tile_h (host only)
+void det_items_build(vsfe_batch *b);
+// launch the detector over n device items (no argument checks)
+int32_t detect_launch(const vsfe_ctx *ctx, const vsfe_batch *b, const DetItem *items, int32_t n_items,
+                      const uint8_t *images, const uint8_t *pyr, const uint8_t *cell_mask, uint32_t *cell_keys,
+                      uint16_t *crf_debug, hipStream_t st);
 
 // one-time upload of the orientation disc tables to the current device
 int32_t orb_prepare(int device);

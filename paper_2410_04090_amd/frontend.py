@@ -117,6 +117,21 @@ class Frontend:
                 vsfe.stereo_match(c, b, self.kps, self.kp_count, self.desc, self.match_idx, self.match_dist,
                                   self.match_disp, self.status, stream)
 
+    def autotune(self, reps=5):
+        """Pick per-level detector tiles on the uploaded batch (graphs captured
+        before must be captured again)."""
+        vsfe.pyramid_build(self.ctx, self.batch, self.images, self.pyr, self.status)
+        rep = vsfe.batch_autotune(self.ctx, self.batch, self.images, self.pyr, self.cell_keys, self.status, reps)
+        self._graph = None
+        return rep.as_dict()
+
+    def tiles(self):
+        return vsfe.batch_tiles_get(self.batch, self.params.n_levels)
+
+    def set_tiles(self, tile_w, tile_h):
+        vsfe.batch_set_tiles(self.batch, tile_w, tile_h)
+        self._graph = None
+
     def cnn_geometry(self, image):
         """(W3, H3, Wz, Hz) of one image's proposer grid."""
         li = self.level_info(image, 3)

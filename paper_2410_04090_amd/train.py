@@ -5,12 +5,17 @@ each generated pair (cells holding the native-scale position of a final
 keypoint), cnn_forward / cnn_backward compute the weighted binary
 cross-entropy gradient and cnn_adam_step updates the weights.  Scenes come
 from the seeded generator (200 polygons, blur 1, noise 3, disparities
-0..64) at 1241 x 376; training seeds are 10^6 + i, held-out seeds
-2 * 10^6 + i.  The held-out pass picks the largest threshold whose gated
-path keeps >= 99% of the exact path's keypoints, and does the same for a
-non-learned baseline (level-3 intensity range per cell).
+0..64) at 1241 x 376 ("kitti": training seeds 10^6 + i, held-out seeds
+2 * 10^6 + i) or (800 polygons, disparities 0..128, at most 4000
+keypoints) at 1920 x 1080 ("hd": 3 * 10^6 + i and 4 * 10^6 + i).  The
+held-out pass picks the largest threshold whose gated path keeps >= 99%
+of the exact path's keypoints, and does the same for a non-learned
+baseline (level-3 intensity range per cell); thresholds are stored per
+image size with the weights.
 
     python -m paper_2410_04090_amd.train --pairs 50000 --out gpurun_out/proposer.npz
+    python -m paper_2410_04090_amd.train --scene hd --init gpurun_out/proposer.npz --pairs 8000 \\
+        --batch 16 --out gpurun_out/proposer_hd.npz
 """
 from __future__ import annotations
 
@@ -27,22 +32,43 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-W_IMG, H_IMG = 1241, 376
-TRAIN_SEED0, EVAL_SEED0 = 1_000_000, 2_000_000
+class Scene:
+    """Generator settings and detection parameters of one training domain."""
+
+    def __init__(self, name, w, h, polys, max_disp, params_kw, seed_train, seed_eval):
+        self.name, self.w, self.h, self.polys, self.max_disp = name, w, h, polys, max_disp
+        self.params_kw, self.seed_train, self.seed_eval = params_kw, seed_train, seed_eval
+
+    def params(self):
+        from synth.configs import Params
+        return Params(**self.params_kw)
+
+    @property
+    def size(self):
+        return "%dx%d" % (self.w, self.h)
 
 
-def _gen(seed):
+SCENES = {
+    # KITTI-shaped pairs: 200 polygons, disparities 0..64, at most 2000 keypoints
+    "kitti": Scene("kitti", 1241, 376, 200, 64, {}, 1_000_000, 2_000_000),
+    # 1080p pairs: 800 polygons, disparities 0..128, at most 4000 keypoints
+    "hd": Scene("hd", 1920, 1080, 800, 128, {"n_max": 4000, "d_max": 128}, 3_000_000, 4_000_000),
+}
+
+
+def _gen(job):
     from synth import scenes
-    return scenes.stereo_pair(seed, W_IMG, H_IMG, 200, 64)
+    seed, w, h, polys, dmax = job
+    return scenes.stereo_pair(seed, w, h, polys, dmax)
 
 
-def pair_batches(seed0, n_pairs, batch, procs):
+def pair_batches(scene, seed0, n_pairs, batch, procs):
     """Yield lists of `batch` pairs (left, right), generated in worker processes."""
     import multiprocessing as mp
-    seeds = list(range(seed0, seed0 + n_pairs))
+    jobs = [(s, scene.w, scene.h, scene.polys, scene.max_disp) for s in range(seed0, seed0 + n_pairs)]
     with mp.get_context("fork").Pool(procs) as pool:
         buf = []
-        for pair in pool.imap(_gen, seeds, chunksize=4):
+        for pair in pool.imap(_gen, jobs, chunksize=4):
             buf.append(pair)
             if len(buf) == batch:
                 yield buf
@@ -54,15 +80,15 @@ def pair_batches(seed0, n_pairs, batch, procs):
 class Proposer:
     """Frontend + proposer state for batches of same-size stereo pairs."""
 
-    def __init__(self, batch_pairs, init_seed=7, lr=2e-3):
+    def __init__(self, scene, batch_pairs, init_seed=7, lr=2e-3):
         import torch
         from synth import pattern as pat
-        from synth.configs import Params
         from . import vsfe
         from .frontend import Frontend
         self.torch, self.vsfe = torch, vsfe
-        self.params = Params()
-        self.fe = Frontend(self.params, [(W_IMG, H_IMG)] * (2 * batch_pairs), pat.brief_pattern())
+        self.scene = scene
+        self.params = scene.params()
+        self.fe = Frontend(self.params, [(scene.w, scene.h)] * (2 * batch_pairs), pat.brief_pattern())
         self.offs = self.fe.grid_offsets()
         theta = np.concatenate([p.reshape(-1) for p in pat.cnn_init(init_seed)]).astype(np.float32)
         dev = "cuda"
@@ -101,10 +127,11 @@ class Proposer:
         t = np.zeros(self.targets.numel(), np.float32)
         cells = []
         for i, (x0, y0, _) in enumerate(kps):
-            lab = labels.positive_cells(x0, y0, W_IMG, H_IMG)
+            W, H = self.scene.w, self.scene.h
+            lab = labels.positive_cells(x0, y0, W, H)
             cells.append(lab)
             off, hz, wz = self.offs[i]
-            t[off:off + hz * wz] = labels.grid_targets(lab, W_IMG, H_IMG, wz, hz).reshape(-1)
+            t[off:off + hz * wz] = labels.grid_targets(lab, W, H, wz, hz).reshape(-1)
         self.targets.copy_(self.torch.from_numpy(t))
         return cells
 
@@ -130,11 +157,11 @@ class Proposer:
         np.savez(path, params=self.w.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
                  step=self.step_no, meta=json.dumps(meta))
 
-    def load(self, path):
+    def load(self, path, weights_only=False):
         d = np.load(path, allow_pickle=False)
         self.w.copy_(self.torch.from_numpy(d["params"].astype(np.float32)))
         self.wb.copy_(self.w.to(self.torch.bfloat16).view(self.torch.int16))
-        if "m" in d:
+        if "m" in d and not weights_only:
             self.m.copy_(self.torch.from_numpy(d["m"]))
             self.v.copy_(self.torch.from_numpy(d["v"]))
             self.step_no = int(d["step"])
@@ -160,9 +187,10 @@ def evaluate(prop, n_pairs, batch, procs, n_tau=12):
     """Held-out recall / precision / kept-cell fraction for the CNN and the
     contrast baseline over candidate thresholds."""
     from . import labels
-    fe, torch, vs = prop.fe, prop.torch, prop.vsfe
+    fe, torch, vs, sc = prop.fe, prop.torch, prop.vsfe, prop.scene
+    W, H = sc.w, sc.h
     batches = []
-    for pairs in pair_batches(EVAL_SEED0, n_pairs, batch, procs):
+    for pairs in pair_batches(sc, sc.seed_eval, n_pairs, batch, procs):
         imgs = [im for pr in pairs for im in pr]
         if len(imgs) < fe.n:
             imgs = (imgs * (fe.n // len(imgs) + 1))[:fe.n]
@@ -172,9 +200,9 @@ def evaluate(prop, n_pairs, batch, procs, n_tau=12):
                        fe.cell_mask, fe.status)
         torch.cuda.synchronize()
         cl = fe.cell_logits.cpu().numpy().copy()
-        con = np.concatenate([labels.contrast_scores(fe.pyramid_levels(i)[3], W_IMG, H_IMG).reshape(-1)
+        con = np.concatenate([labels.contrast_scores(fe.pyramid_levels(i)[3], W, H).reshape(-1)
                               for i in range(fe.n)])
-        pos = np.concatenate([labels.positive_cells(k[0], k[1], W_IMG, H_IMG).reshape(-1) for k in kps])
+        pos = np.concatenate([labels.positive_cells(k[0], k[1], W, H).reshape(-1) for k in kps])
         batches.append((imgs, [k[2] for k in kps], cl, con, pos))
     all_cl = np.concatenate([b[2] for b in batches])
     all_con = np.concatenate([b[3] for b in batches])
@@ -211,6 +239,7 @@ def evaluate(prop, n_pairs, batch, procs, n_tau=12):
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--scene", default="kitti", choices=sorted(SCENES))
     ap.add_argument("--pairs", type=int, default=50000)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--eval-pairs", type=int, default=1000)
@@ -218,34 +247,46 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--pos-weight", type=float, default=1.0)
     ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "proposer.npz"))
-    ap.add_argument("--resume", default=None)
+    ap.add_argument("--resume", default=None, help="continue from a checkpoint (weights + Adam state)")
+    ap.add_argument("--init", default=None, help="start from a checkpoint's weights with a fresh optimizer")
     ap.add_argument("--eval-only", action="store_true")
     args = ap.parse_args()
-    prop = Proposer(args.batch, lr=args.lr)
+    sc = SCENES[args.scene]
+    prop = Proposer(sc, args.batch, lr=args.lr)
     meta = {}
     if args.resume:
         meta = prop.load(args.resume)
-    total = (args.pairs + args.batch - 1) // args.batch
+    elif args.init:
+        meta = prop.load(args.init, weights_only=True)
+    meta = dict(meta)
     t0 = time.time()
     if not args.eval_only:
+        history = meta.pop("history", [])
+        prev = {k: meta[k] for k in ("scene", "pairs", "train_seed0", "final_loss") if k in meta}
+        if prev:
+            history.append(prev)
+        total = (args.pairs + args.batch - 1) // args.batch
         losses = []
-        for k, pairs in enumerate(pair_batches(TRAIN_SEED0, args.pairs, args.batch, args.procs)):
+        for k, pairs in enumerate(pair_batches(sc, sc.seed_train, args.pairs, args.batch, args.procs)):
             losses.append(prop.train_step(pairs, total, args.pos_weight))
             if (k + 1) % 50 == 0 or k + 1 == total:
                 print("step %d/%d loss %.4f (%.0f s)" % (k + 1, total, float(np.mean(losses[-50:])), time.time() - t0),
                       flush=True)
             if (k + 1) % 500 == 0:
-                prop.save(args.out, {"pairs_seen": (k + 1) * args.batch, "train_seed0": TRAIN_SEED0})
-        meta = {"pairs": args.pairs, "batch": args.batch, "lr": args.lr, "pos_weight": args.pos_weight,
-                "train_seed0": TRAIN_SEED0, "final_loss": float(np.mean(losses[-50:])) if losses else None,
-                "train_seconds": time.time() - t0}
-        prop.save(args.out, meta)
+                prop.save(args.out, {"pairs_seen": (k + 1) * args.batch, "scene": sc.name})
+        # new weights: earlier evaluations no longer apply
+        meta = {"scene": sc.name, "pairs": args.pairs, "batch": args.batch, "lr": args.lr,
+                "pos_weight": args.pos_weight, "train_seed0": sc.seed_train,
+                "final_loss": float(np.mean(losses[-50:])) if losses else None, "train_seconds": time.time() - t0,
+                "history": history}
     ev = evaluate(prop, args.eval_pairs, args.batch, args.procs)
-    meta["eval"] = ev
-    meta["eval_seed0"] = EVAL_SEED0
-    meta["eval_pairs"] = args.eval_pairs
+    evals = dict(meta.get("evals", {}))
+    evals[sc.size] = {"seed0": sc.seed_eval, "pairs": args.eval_pairs, **ev}
+    meta["evals"] = evals
+    meta["thresholds"] = {k: v["cnn_chosen"]["thresh"] for k, v in evals.items() if v.get("cnn_chosen")}
     prop.save(args.out, meta)
-    print(json.dumps({"eval": {k: ev[k] for k in ("pos_frac", "cnn_chosen", "contrast_chosen")}}), flush=True)
+    print(json.dumps({"scene": sc.name, "eval": {k: ev[k] for k in ("pos_frac", "cnn_chosen", "contrast_chosen")}}),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -61,11 +61,24 @@ class CnnInfo(C.Structure):
                 ("n_params", C.c_int32)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("tile_w", C.c_int32 * MAX_LEVELS), ("tile_h", C.c_int32 * MAX_LEVELS),
+                ("us", C.c_float * MAX_LEVELS), ("us_before", C.c_float * MAX_LEVELS),
+                ("n_tried", C.c_int32 * MAX_LEVELS)]
+
+    def as_dict(self):
+        n = self.n_levels
+        return {"tile_w": list(self.tile_w[:n]), "tile_h": list(self.tile_h[:n]),
+                "us": [round(x, 2) for x in self.us[:n]], "us_before": [round(x, 2) for x in self.us_before[:n]],
+                "n_tried": list(self.n_tried[:n])}
+
+
 EXPORTS = ["vsfe_params_default", "vsfe_params_check", "vsfe_level_geometry", "vsfe_ctx_create",
            "vsfe_ctx_destroy", "vsfe_batch_create", "vsfe_batch_destroy", "vsfe_batch_plan",
            "vsfe_batch_info_get", "vsfe_batch_level_info", "vsfe_ctx_set_tile", "vsfe_last_error",
            "pyramid_build", "fast_br_detect", "pyca_cull_aggregate", "orb_describe", "stereo_match",
-           "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step"]
+           "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step",
+           "vsfe_batch_tiles_get", "vsfe_batch_set_tiles", "vsfe_batch_autotune"]
 
 _lib = None
 
@@ -102,6 +115,12 @@ def lib():
     L.vsfe_batch_info_get.restype = i32
     L.vsfe_batch_level_info.argtypes = [vp, i32, i32, C.POINTER(LevelInfo)]
     L.vsfe_batch_level_info.restype = i32
+    L.vsfe_batch_tiles_get.argtypes = [vp, pi32, pi32]
+    L.vsfe_batch_tiles_get.restype = i32
+    L.vsfe_batch_set_tiles.argtypes = [vp, pi32, pi32]
+    L.vsfe_batch_set_tiles.restype = i32
+    L.vsfe_batch_autotune.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, C.POINTER(TuneReport)]
+    L.vsfe_batch_autotune.restype = i32
     L.vsfe_last_error.argtypes = []
     L.vsfe_last_error.restype = C.c_char_p
     L.pyramid_build.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -214,6 +233,25 @@ def batch_level_info(b, image, level) -> LevelInfo:
     li = LevelInfo()
     _check(lib().vsfe_batch_level_info(b, image, level, C.byref(li)))
     return li
+
+
+def batch_tiles_get(b, n_levels):
+    w, h = (C.c_int32 * MAX_LEVELS)(), (C.c_int32 * MAX_LEVELS)()
+    _check(lib().vsfe_batch_tiles_get(b, w, h))
+    return list(w[:n_levels]), list(h[:n_levels])
+
+
+def batch_set_tiles(b, tile_w, tile_h):
+    w = (C.c_int32 * MAX_LEVELS)(*tile_w)
+    h = (C.c_int32 * MAX_LEVELS)(*tile_h)
+    _check(lib().vsfe_batch_set_tiles(b, w, h))
+
+
+def batch_autotune(ctx, b, images, pyr, cell_keys, status, reps=5, stream=None) -> TuneReport:
+    rep = TuneReport()
+    _check(lib().vsfe_batch_autotune(ctx, b, _p(images), _p(pyr), _p(cell_keys), _p(status), reps,
+                                     _stream(stream), C.byref(rep)))
+    return rep
 
 
 def kp_soa(kps: dict) -> KpSoa:

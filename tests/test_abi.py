@@ -88,3 +88,13 @@ def test_pattern_outside_disc_rejected():
     with pytest.raises(vsfe.VsfeError) as e:
         vsfe.ctx_create(p, pat)
     assert e.value.code == vsfe.EINVAL
+
+
+def test_autotune_and_tiles_reject_null_arguments():
+    lib = vsfe.lib()
+    rep = vsfe.TuneReport()
+    w = (C.c_int32 * vsfe.MAX_LEVELS)(*([64] * vsfe.MAX_LEVELS))
+    assert lib.vsfe_batch_autotune(None, None, None, None, None, None, 3, None, C.byref(rep)) == vsfe.EINVAL
+    assert lib.vsfe_batch_set_tiles(None, w, w) == vsfe.EINVAL
+    assert lib.vsfe_batch_tiles_get(None, w, w) == vsfe.EINVAL
+    assert b"null" in lib.vsfe_last_error()

@@ -119,6 +119,37 @@ def test_propose_cells_and_mask(torch_mod):
         fe.close()
 
 
+def test_fused_inference_equals_layerwise_forward(torch_mod):
+    """cnn_propose (one fused kernel per 8 x 8 tile, activations in LDS) gives
+    bit-identical grid logits to cnn_forward (layer by layer through HBM), and
+    both match the oracle; sizes include tiles cut by every border."""
+    torch = torch_mod
+    imgs = images_mixed() + [scenes.random_image(4004, 61, 47), scenes.mono_image(4005, 203, 333, 40)]
+    p = Params()
+    theta = theta_for(15)
+    fe = make_batch(torch, imgs, p)
+    try:
+        from paper_2410_04090_amd import vsfe
+        fe.run(describe=False)
+        w = bf16_tensor(torch, theta)
+        vsfe.cnn_forward(fe.ctx, fe.batch, fe.pyr, w, fe.cnn_ws, fe.grid_logits, fe.status)
+        torch.cuda.synchronize()
+        z_fwd = fe.grid_logits.cpu().numpy().copy()
+        fe.grid_logits.fill_(float("nan"))
+        vsfe.cnn_propose(fe.ctx, fe.batch, fe.pyr, w, 0.0, fe.cnn_ws, fe.grid_logits, fe.cell_logits, fe.cell_mask,
+                         fe.status)
+        torch.cuda.synchronize()
+        z_fused = fe.grid_logits.cpu().numpy()
+        assert np.array_equal(z_fwd.view(np.uint32), z_fused.view(np.uint32))
+        for i, img in enumerate(imgs):
+            ref, _ = ocnn.forward(oracle.pyramid(img, 4)[3], theta, bf16=True)
+            err = np.abs(grid_of(fe, z_fused, i) - ref).max()
+            say("image", i, img.shape, "fused max |dz| =", err)
+            assert err <= 1e-2
+    finally:
+        fe.close()
+
+
 def test_backward_matches_oracle(torch_mod):
     torch = torch_mod
     imgs = [scenes.mono_image(4010, 640, 480, 120), scenes.random_image(4011, 420, 300)]
