@@ -11,10 +11,10 @@
 //
 //  * conv1 (K = 9 taps, padded to 16) runs on v_mfma_f32_16x16x16_bf16;
 //  * conv2 (K = 144) and conv3 (K = 288) are implicit GEMMs on
-//    v_mfma_f32_16x16x32_bf16: one wave computes 16 output pixels x 32
-//    channels, each lane feeding 8 consecutive channels of one tap as its
+//    v_mfma_f32_16x16x32_bf16: one wave computes 32 channels x 16 output
+//    pixels, each lane feeding 8 consecutive channels of one tap as its
 //    K slice (weights repacked to [co][tap][ci]); the 1x1 head is fused in
-//    conv3's epilogue with a 16-lane shuffle reduction;
+//    conv3's epilogue with a shuffle reduction over the channel groups;
 //  * inference (cnn_propose) runs the three layers and the head fused in
 //    one kernel per 4 x 8 tile of grid positions, activations in LDS; the
 //    layer-by-layer kernels (cnn_forward) keep the activations for training;
@@ -86,27 +86,59 @@ __global__ void cnn_pack_kernel(const uint16_t *__restrict__ prm, uint16_t *__re
     }
 }
 
-// conv1 (1 -> 16, K = 9 taps) on v_mfma_f32_16x16x16_bf16: M = 16 output
-// pixels, N = 16 channels, K = the 9 taps zero-padded to 16; lane l feeds
-// taps 4 (l / 16) .. 4 (l / 16) + 3 of pixel l % 16.  The input x = (I - 128)
-// / 128 is exact in bfloat16.  Both forward paths use these helpers, so
-// their conv1 outputs are identical.
+// All three convolutions run on MFMA with the weights as the A operand
+// (row = output channel) and the activations as the B operand (column =
+// output pixel), so each lane ends with 4 consecutive channels of one pixel
+// and stores them as one 8-byte NHWC write.  Lane l: pixel l % 16, K slice
+// (l / 16); accumulator r of lane l is channel 4 (l / 16) + r.  Both forward
+// paths use the helpers below, so their activations and logits are
+// bit-identical.
+//
+// conv1 (1 -> 16, K = 9 taps zero-padded to 16) on v_mfma_f32_16x16x16_bf16;
+// the input x = (I - 128) / 128 is exact in bfloat16.
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t x_bf(int v) { return to_bf((float)(v - 128) * (1.0f / 128.0f)); }
 
-// this lane's B operand: w1[n][k] for its 4 taps k (0 beyond the ninth)
+// A operand of conv1: w1[c][k] for channel c = lane % 16 and the lane's 4 taps
 __device__ __forceinline__ i16x4 conv1_weights(const uint16_t *prm, int lane) {
-    const int n = lane & 15, k0 = 4 * (lane >> 4);
-    i16x4 b;
+    const int c = lane & 15, k0 = 4 * (lane >> 4);
+    i16x4 w;
 #pragma unroll
-    for (int j = 0; j < 4; j++) b[j] = (short)(k0 + j < 9 ? prm[P_W1 + n * 9 + k0 + j] : 0);
-    return b;
+    for (int j = 0; j < 4; j++) w[j] = (short)(k0 + j < 9 ? prm[P_W1 + c * 9 + k0 + j] : 0);
+    return w;
 }
 
-__device__ __forceinline__ f32x4 conv1_mfma(i16x4 a, i16x4 b) {
+__device__ __forceinline__ f32x4 conv1_mfma(i16x4 w, i16x4 x) {
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, zero, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, x, zero, 0, 0, 0);
+}
+
+// bias + ReLU + bfloat16 of 4 consecutive channels, packed for one 8-byte store
+__device__ __forceinline__ uint2 relu_pack4(f32x4 acc, const float *bias) {
+    uint16_t v[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) v[r] = to_bf(fmaxf(acc[r] + bias[r], 0.0f));
+    return make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16));
+}
+
+__device__ __forceinline__ float bf_lo(uint32_t v) { return bf((uint16_t)(v & 0xFFFFu)); }
+__device__ __forceinline__ float bf_hi(uint32_t v) { return bf((uint16_t)(v >> 16)); }
+
+// 1x1 head partial of one lane (its 8 channels), fixed order
+__device__ __forceinline__ float head_part(uint2 p0, uint2 p1, const float *h0, const float *h1) {
+    float s = 0.f;
+    s += h0[0] * bf_lo(p0.x);
+    s += h0[1] * bf_hi(p0.x);
+    s += h0[2] * bf_lo(p0.y);
+    s += h0[3] * bf_hi(p0.y);
+    s += h1[0] * bf_lo(p1.x);
+    s += h1[1] * bf_hi(p1.x);
+    s += h1[2] * bf_lo(p1.y);
+    s += h1[3] * bf_hi(p1.y);
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return s;
 }
 
 // One wave: 16 consecutive conv1 pixels of one image (row-major), NHWC out.
@@ -120,36 +152,57 @@ __global__ __launch_bounds__(256) void cnn_conv1_kernel(const CnnImg *__restrict
     const int i = find_image(pre_tiles, n, tile);
     const CnnImg im = imgs[i];
     const int npx = im.w1 * im.h1;
-    const int p0 = (int)(tile - pre_tiles[i]) * 16;
     const int m = lane & 15, grp = lane >> 4;
-    const int pm = p0 + m;
+    const int pm = (int)(tile - pre_tiles[i]) * 16 + m;
     const int oy = pm / im.w1, ox = pm - oy * im.w1;
-    i16x4 a;
+    i16x4 x;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int k = 4 * grp + j;
         const int iy = 2 * oy + k / 3 - 1, ix = 2 * ox + k % 3 - 1;
         const bool in = pm < npx && k < 9 && iy >= 0 && iy < im.h3 && ix >= 0 && ix < im.w3;
-        a[j] = (short)(in ? x_bf(pyr[im.lvl3 + (int64_t)iy * im.pitch3 + ix]) : 0);
+        x[j] = (short)(in ? x_bf(pyr[im.lvl3 + (int64_t)iy * im.pitch3 + ix]) : 0);
     }
-    const f32x4 acc = conv1_mfma(a, conv1_weights(prm, lane));
-    const float bias = bf(prm[P_B1 + m]);
+    const f32x4 acc = conv1_mfma(conv1_weights(prm, lane), x);
+    float bias[4];
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-        const int p = p0 + 4 * grp + r;
-        if (p < npx) a1[(im.px1 + p) * 16 + m] = to_bf(fmaxf(acc[r] + bias, 0.0f));
+    for (int r = 0; r < 4; r++) bias[r] = bf(prm[P_B1 + 4 * grp + r]);
+    if (pm < npx) *(uint2 *)(a1 + (im.px1 + pm) * 16 + 4 * grp) = relu_pack4(acc, bias);
+}
+
+// Implicit-GEMM 3x3 stride-2 convolution CIN -> 32: K chunks of 32 (conv2:
+// pairs of taps x 16 channels, the last padded; conv3: one tap x 32
+// channels); A = packed weights [co][tap][ci], B = 8 channels of one tap of
+// the lane's pixel.  Returns through acc0 (channels 0..15) and acc1 (16..31).
+template <int CIN>
+__device__ __forceinline__ void conv_weights(const uint16_t *wp, int lane, uint4 *w0, uint4 *w1) {
+    constexpr int NCH = CIN == 16 ? 5 : 9;
+    const int m = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int c = 0; c < NCH; c++) {
+        const int t = CIN == 16 ? 2 * c + (grp >> 1) : c;
+        const int ci0 = CIN == 16 ? 8 * (grp & 1) : 8 * grp;
+        w0[c] = w1[c] = make_uint4(0, 0, 0, 0);
+        if (t < 9) {
+            w0[c] = *(const uint4 *)(wp + ((m * 9 + t) * CIN + ci0));
+            w1[c] = *(const uint4 *)(wp + (((m + 16) * 9 + t) * CIN + ci0));
+        }
     }
 }
 
-// Implicit-GEMM 3x3 stride-2 convolution CIN -> 32 on MFMA; with HEAD the
-// 1x1 head is applied to the (bf16-rounded) outputs and z is written.
+__device__ __forceinline__ void conv_mfma2(uint4 xv, uint4 w0, uint4 w1, f32x4 &acc0, f32x4 &acc1) {
+    const bf16x8 x = __builtin_bit_cast(bf16x8, xv);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w0), x, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w1), x, acc1, 0, 0, 0);
+}
+
 template <int CIN, bool HEAD>
 __global__ __launch_bounds__(256) void cnn_conv_mfma_kernel(const CnnImg *__restrict__ imgs,
                                                             const int32_t *__restrict__ pre_tiles, int n,
                                                             int64_t total_tiles, const uint16_t *__restrict__ ain,
                                                             uint16_t *__restrict__ aout, const uint16_t *__restrict__ wp,
                                                             const uint16_t *__restrict__ prm, float *__restrict__ z) {
-    constexpr int NCH = CIN == 16 ? 5 : 9;     // K chunks of 32 (conv2: pairs of taps, the last padded)
+    constexpr int NCH = CIN == 16 ? 5 : 9;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
     if (tile >= total_tiles) return;
@@ -159,70 +212,54 @@ __global__ __launch_bounds__(256) void cnn_conv_mfma_kernel(const CnnImg *__rest
     const int out_w = CIN == 16 ? im.w2 : im.w4, out_h = CIN == 16 ? im.h2 : im.h4;
     const int64_t in_base = CIN == 16 ? im.px1 : im.px2, out_base = CIN == 16 ? im.px2 : im.px4;
     const int npx = out_w * out_h;
-    const int p0 = (int)(tile - pre_tiles[i]) * 16;
     const int m = lane & 15, grp = lane >> 4;
-    const int pm = p0 + m;
+    const int pm = (int)(tile - pre_tiles[i]) * 16 + m;
     const bool valid = pm < npx;
     const int oy = valid ? pm / out_w : 0, ox = valid ? pm - oy * out_w : 0;
+    uint4 w0[NCH], w1[NCH];
+    conv_weights<CIN>(wp, lane, w0, w1);
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int c = 0; c < NCH; c++) {
         const int t = CIN == 16 ? 2 * c + (grp >> 1) : c;
         const int ci0 = CIN == 16 ? 8 * (grp & 1) : 8 * grp;
-        uint4 av = make_uint4(0, 0, 0, 0), b0 = make_uint4(0, 0, 0, 0), b1 = make_uint4(0, 0, 0, 0);
+        uint4 xv = make_uint4(0, 0, 0, 0);
         if (t < 9) {
             const int iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
             if (valid && iy >= 0 && iy < in_h && ix >= 0 && ix < in_w)
-                av = *(const uint4 *)(ain + ((in_base + (int64_t)iy * in_w + ix) * CIN + ci0));
-            b0 = *(const uint4 *)(wp + ((m * 9 + t) * CIN + ci0));
-            b1 = *(const uint4 *)(wp + (((m + 16) * 9 + t) * CIN + ci0));
+                xv = *(const uint4 *)(ain + ((in_base + (int64_t)iy * in_w + ix) * CIN + ci0));
         }
-        const bf16x8 a = __builtin_bit_cast(bf16x8, av);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
+        conv_mfma2(xv, w0[c], w1[c], acc0, acc1);
     }
-    // lane holds output channels m and m + 16 of pixels p0 + 4 grp + r
     const int bias_at = CIN == 16 ? P_B2 : P_B3;
-    const float bb0 = bf(prm[bias_at + m]), bb1 = bf(prm[bias_at + m + 16]);
-    float hw0 = 0.f, hw1 = 0.f;
-    if (HEAD) {
-        hw0 = bf(prm[P_W4 + m]);
-        hw1 = bf(prm[P_W4 + m + 16]);
-    }
-    float part[4];
+    float b0[4], b1[4];
 #pragma unroll
     for (int r = 0; r < 4; r++) {
-        const int p = p0 + 4 * grp + r;
-        const uint16_t v0 = to_bf(fmaxf(acc0[r] + bb0, 0.0f)), v1 = to_bf(fmaxf(acc1[r] + bb1, 0.0f));
-        if (p < npx) {
-            aout[(out_base + p) * 32 + m] = v0;
-            aout[(out_base + p) * 32 + m + 16] = v1;
-        }
-        part[r] = hw0 * bf(v0) + hw1 * bf(v1);
+        b0[r] = bf(prm[bias_at + 4 * grp + r]);
+        b1[r] = bf(prm[bias_at + 16 + 4 * grp + r]);
+    }
+    const uint2 v0 = relu_pack4(acc0, b0), v1 = relu_pack4(acc1, b1);
+    if (valid) {
+        *(uint2 *)(aout + (out_base + pm) * 32 + 4 * grp) = v0;
+        *(uint2 *)(aout + (out_base + pm) * 32 + 16 + 4 * grp) = v1;
     }
     if (HEAD) {
+        float h0[4], h1[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-#pragma unroll
-            for (int o = 8; o > 0; o >>= 1) part[r] += __shfl_xor(part[r], o);
+            h0[r] = bf(prm[P_W4 + 4 * grp + r]);
+            h1[r] = bf(prm[P_W4 + 16 + 4 * grp + r]);
         }
-        if (m == 0) {
-            const float b4 = bf(prm[P_B4]);
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int p = p0 + 4 * grp + r;
-                if (p < npx) z[out_base + p] = part[r] + b4;
-            }
-        }
+        const float part = head_part(v0, v1, h0, h1);
+        if (grp == 0 && valid) z[out_base + pm] = part + bf(prm[P_B4]);
     }
 }
 
 // Fused inference forward: one 256-thread block computes a 4 x 8 tile of
 // grid logits with every intermediate activation in LDS (level-3 input
 // 39 x 71, conv1 19 x 35 x 16, conv2 9 x 17 x 32; positions outside an
-// activation map are its zero padding).  Same operand layout, chunk order
-// and rounding points as the layer-by-layer kernels, so the logits are
-// bit-identical to cnn_forward's.
+// activation map are its zero padding).  Same helpers as the layer-by-layer
+// kernels, so the logits are bit-identical to cnn_forward's.
 constexpr int CF3H = 4, CF3W = 8;                         // grid positions per tile
 constexpr int CF2H = 2 * CF3H + 1, CF2W = 2 * CF3W + 1;   // conv2 window  9 x 17
 constexpr int CF1H = 2 * CF2H + 1, CF1W = 2 * CF2W + 1;   // conv1 window 19 x 35
@@ -264,7 +301,6 @@ __global__ __launch_bounds__(256) void cnn_fused_fwd_kernel(const CnnImg *__rest
             const int gy = Y0 + rr, gx = X0 - 1 + 4 * j;
             const bool ok = d < CF0H * CF0D && gy >= 0 && gy < im.h3 && gx >= 0 && gx < im.w3;
             v[k] = ok ? *(const uint32_t *)(pyr + im.lvl3 + (int64_t)gy * im.pitch3 + gx) : 0u;
-            if (ok && gx + 4 > im.w3) v[k] &= 0xFFFFFFFFu >> (8 * (gx + 4 - im.w3));
         }
 #pragma unroll
         for (int k = 0; k < CF_LD; k++) {
@@ -283,10 +319,12 @@ __global__ __launch_bounds__(256) void cnn_fused_fwd_kernel(const CnnImg *__rest
     }
     __syncthreads();
 
-    // B. conv1
+    // B. conv1: one pixel per lane and M tile, 4 channels per lane
     {
-        const i16x4 b = conv1_weights(prm, lane);
-        const float bias = bf(prm[P_B1 + m]);
+        const i16x4 w = conv1_weights(prm, lane);
+        float bias[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) bias[r] = bf(prm[P_B1 + 4 * grp + r]);
         int toff[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
@@ -298,36 +336,28 @@ __global__ __launch_bounds__(256) void cnn_fused_fwd_kernel(const CnnImg *__rest
             const int p = 16 * t + m;
             const int r1 = p / CF1W, c1 = p - r1 * CF1W;
             const int base = 2 * r1 * CF0S + 2 * c1;
-            i16x4 a;
+            i16x4 x;
 #pragma unroll
-            for (int j = 0; j < 4; j++) a[j] = (short)(p < CF1N && toff[j] >= 0 ? s_u[base + toff[j]] : 0);
-            const f32x4 acc = conv1_mfma(a, b);
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int q = 16 * t + 4 * grp + r;
-                if (q < CF1N) {
-                    const int qy = q / CF1W, qx = q - qy * CF1W;
-                    const bool in = qy >= vy0 && qy < vy1 && qx >= vx0 && qx < vx1;
-                    s_a1[q * 16 + m] = in ? to_bf(fmaxf(acc[r] + bias, 0.0f)) : (uint16_t)0;
-                }
+            for (int j = 0; j < 4; j++) x[j] = (short)(p < CF1N && toff[j] >= 0 ? s_u[base + toff[j]] : 0);
+            const f32x4 acc = conv1_mfma(w, x);
+            if (p < CF1N) {
+                const bool in = r1 >= vy0 && r1 < vy1 && c1 >= vx0 && c1 < vx1;
+                *(uint2 *)(s_a1 + p * 16 + 4 * grp) = in ? relu_pack4(acc, bias) : make_uint2(0, 0);
             }
         }
     }
     __syncthreads();
 
-    // C. conv2 (16 -> 32), K chunks = pairs of taps x 16 channels
+    // C. conv2 (16 -> 32)
     {
         uint4 w0[5], w1[5];
+        conv_weights<16>(wp2, lane, w0, w1);
+        float b0[4], b1[4];
 #pragma unroll
-        for (int c = 0; c < 5; c++) {
-            const int t = 2 * c + (grp >> 1), ci0 = 8 * (grp & 1);
-            w0[c] = w1[c] = make_uint4(0, 0, 0, 0);
-            if (t < 9) {
-                w0[c] = *(const uint4 *)(wp2 + ((m * 9 + t) * 16 + ci0));
-                w1[c] = *(const uint4 *)(wp2 + (((m + 16) * 9 + t) * 16 + ci0));
-            }
+        for (int r = 0; r < 4; r++) {
+            b0[r] = bf(prm[P_B2 + 4 * grp + r]);
+            b1[r] = bf(prm[P_B2 + 16 + 4 * grp + r]);
         }
-        const float bb0 = bf(prm[P_B2 + m]), bb1 = bf(prm[P_B2 + m + 16]);
         const int vy0 = max(0, -Y2), vy1 = min(CF2H, im.h2 - Y2), vx0 = max(0, -X2), vx1 = min(CF2W, im.w2 - X2);
         for (int t2 = wave; t2 < (CF2N + 15) / 16; t2 += 4) {
             const int p = 16 * t2 + m;
@@ -337,24 +367,14 @@ __global__ __launch_bounds__(256) void cnn_fused_fwd_kernel(const CnnImg *__rest
 #pragma unroll
             for (int c = 0; c < 5; c++) {
                 const int t = 2 * c + (grp >> 1), ci0 = 8 * (grp & 1);
-                uint4 av = make_uint4(0, 0, 0, 0);
-                if (t < 9 && valid) {
-                    const int q1 = (2 * r2 + t / 3) * CF1W + (2 * c2 + t % 3);
-                    av = *(const uint4 *)(s_a1 + q1 * 16 + ci0);
-                }
-                const bf16x8 a = __builtin_bit_cast(bf16x8, av);
-                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, w0[c]), acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, w1[c]), acc1, 0, 0, 0);
+                uint4 xv = make_uint4(0, 0, 0, 0);
+                if (t < 9 && valid) xv = *(const uint4 *)(s_a1 + ((2 * r2 + t / 3) * CF1W + (2 * c2 + t % 3)) * 16 + ci0);
+                conv_mfma2(xv, w0[c], w1[c], acc0, acc1);
             }
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int q = 16 * t2 + 4 * grp + r;
-                if (q < CF2N) {
-                    const int qy = q / CF2W, qx = q - qy * CF2W;
-                    const bool in = qy >= vy0 && qy < vy1 && qx >= vx0 && qx < vx1;
-                    s_c2[q * 32 + m] = in ? to_bf(fmaxf(acc0[r] + bb0, 0.0f)) : (uint16_t)0;
-                    s_c2[q * 32 + m + 16] = in ? to_bf(fmaxf(acc1[r] + bb1, 0.0f)) : (uint16_t)0;
-                }
+            if (valid) {
+                const bool in = r2 >= vy0 && r2 < vy1 && c2 >= vx0 && c2 < vx1;
+                *(uint2 *)(s_c2 + p * 32 + 4 * grp) = in ? relu_pack4(acc0, b0) : make_uint2(0, 0);
+                *(uint2 *)(s_c2 + p * 32 + 16 + 4 * grp) = in ? relu_pack4(acc1, b1) : make_uint2(0, 0);
             }
         }
     }
@@ -363,40 +383,25 @@ __global__ __launch_bounds__(256) void cnn_fused_fwd_kernel(const CnnImg *__rest
     // D. conv3 (32 -> 32) + 1x1 head: waves 0 and 1 take tile rows 2w, 2w + 1
     if (wave < CF3H / 2) {
         const int r3 = 2 * wave + (m >> 3), c3 = m & 7;
+        uint4 w0[9], w1[9];
+        conv_weights<32>(wp3, lane, w0, w1);
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 9; t++) {
-            const int ci0 = 8 * grp;
-            const int q2 = (2 * r3 + t / 3) * CF2W + (2 * c3 + t % 3);
-            const uint4 av = *(const uint4 *)(s_c2 + q2 * 32 + ci0);
-            const uint4 b0 = *(const uint4 *)(wp3 + ((m * 9 + t) * 32 + ci0));
-            const uint4 b1 = *(const uint4 *)(wp3 + (((m + 16) * 9 + t) * 32 + ci0));
-            const bf16x8 a = __builtin_bit_cast(bf16x8, av);
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
+            const uint4 xv = *(const uint4 *)(s_c2 + ((2 * r3 + t / 3) * CF2W + (2 * c3 + t % 3)) * 32 + 8 * grp);
+            conv_mfma2(xv, w0[t], w1[t], acc0, acc1);
         }
-        const float bb0 = bf(prm[P_B3 + m]), bb1 = bf(prm[P_B3 + m + 16]);
-        const float hw0 = bf(prm[P_W4 + m]), hw1 = bf(prm[P_W4 + m + 16]);
-        float part[4];
+        float b0[4], b1[4], h0[4], h1[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-            const uint16_t v0 = to_bf(fmaxf(acc0[r] + bb0, 0.0f)), v1 = to_bf(fmaxf(acc1[r] + bb1, 0.0f));
-            part[r] = hw0 * bf(v0) + hw1 * bf(v1);
+            b0[r] = bf(prm[P_B3 + 4 * grp + r]);
+            b1[r] = bf(prm[P_B3 + 16 + 4 * grp + r]);
+            h0[r] = bf(prm[P_W4 + 4 * grp + r]);
+            h1[r] = bf(prm[P_W4 + 16 + 4 * grp + r]);
         }
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-#pragma unroll
-            for (int o = 8; o > 0; o >>= 1) part[r] += __shfl_xor(part[r], o);
-        }
-        if (m == 0) {
-            const float b4 = bf(prm[P_B4]);
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int pr = 4 * grp + r;                 // pixel of this M tile
-                const int gy = Y3 + 2 * wave + (pr >> 3), gx = X3 + (pr & 7);
-                if (gy < im.h4 && gx < im.w4) z[im.px4 + (int64_t)gy * im.w4 + gx] = part[r] + b4;
-            }
-        }
+        const float part = head_part(relu_pack4(acc0, b0), relu_pack4(acc1, b1), h0, h1);
+        const int gy = Y3 + r3, gx = X3 + c3;
+        if (grp == 0 && gy < im.h4 && gx < im.w4) z[im.px4 + (int64_t)gy * im.w4 + gx] = part + bf(prm[P_B4]);
     }
 }
 

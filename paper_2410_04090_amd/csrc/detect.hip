@@ -24,10 +24,11 @@
 //     pixels (0, 4, 8, 12), i.e. one of {0, 8} and one of {4, 12}, so a
 //     bright run needs min(max(p0, p8), max(p4, p12)) > c + eps (dark:
 //     max(min(p0, p8), min(p4, p12)) < c - eps), at the weaker threshold.
-//  3. Each lane collects its candidates in a bit mask over its rows; one
-//     wave prefix sum of the counts places them in a per-wave LDS queue, so
-//     the full ring test runs densely over candidates only (the screen
-//     re-derives the polarity from the same compass test): masks are built with alignbit
+//  3. Each lane collects its candidates in a bit mask over its rows; a wave
+//     prefix sum of the counts on the DPP network places them in the wave's
+//     own LDS queue, so the full ring test runs densely over candidates only
+//     and no block barrier is needed until the cell keys are reduced (the
+//     screen re-derives the polarity from the same compass test): masks are built with alignbit
 //     (one op inserts one sign bit; run lengths do not depend on bit order)
 //     and runs are tested by shift-and doubling.
 //  4. Keys reduce per cell with LDS atomicMax (order independent, so the
@@ -44,8 +45,8 @@ constexpr int FT_W = 100;
 constexpr int FT_MAX_ROWS = 32;
 constexpr int FT_ROWS = FT_MAX_ROWS + 6;
 constexpr int FT_MAX_CELLS = 512;
-constexpr int FT_Q1 = FT_MAX_ROWS * 2 * FT_HALF;   // candidate queue (every tile pixel)
-constexpr int FT_Q2 = 2048;                      // second-stage queue (overflow handled inline)
+constexpr int FT_QW = (FT_MAX_ROWS / 4) * 2 * FT_HALF;   // one wave's candidates (all of its pixels)
+constexpr int FT_Q2W = 512;                               // one wave's survivors (overflow decided inline)
 
 struct DetParams {
     int eps_hi, eps_lo, p_min, p_max, border, eps_min, aligned;
@@ -133,9 +134,27 @@ __global__ __launch_bounds__(256) void expand_mask_kernel(const ImageDev *__rest
     run[lv.cell_offset + idx] = cell_runs(mask0 + im.cell0_offset, im.lv[0], lv, cx, cy) ? 1 : 0;
 }
 
-// 16 consecutive bytes of a row starting at x (zero outside [0, w)).
+// 16 consecutive bytes of a row starting at x (zero outside [0, w)).  In
+// aligned mode x is a multiple of 16 and the row pitch a multiple of 16 that
+// is >= w, so a chunk that starts inside the row is one aligned 16-byte load
+// (bytes past w are masked); otherwise bytes are read one by one.
 __device__ __forceinline__ uint4 fetch16(const uint8_t *row, int x, int w, bool aligned) {
-    if (aligned && x >= 0 && x + 15 < w) return *(const uint4 *)(row + x);
+    if (aligned) {
+        if (x < 0 || x >= w) return make_uint4(0, 0, 0, 0);
+        uint4 v = *(const uint4 *)(row + x);
+        const int valid = w - x;
+        if (valid < 16) {
+            auto keep = [&](int i) {
+                const int k = valid - 4 * i;
+                return k >= 4 ? 0xFFFFFFFFu : (k <= 0 ? 0u : (1u << (8 * k)) - 1u);
+            };
+            v.x &= keep(0);
+            v.y &= keep(1);
+            v.z &= keep(2);
+            v.w &= keep(3);
+        }
+        return v;
+    }
     uint32_t v[4] = {0, 0, 0, 0};
     for (int j = 0; j < 16; j++)
         if (x + j >= 0 && x + j < w) v[j >> 2] |= (uint32_t)row[x + j] << (8 * (j & 3));
@@ -155,6 +174,22 @@ __device__ __forceinline__ uint32_t ring_mask(const int *p, int ctr, int e, bool
     return m;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave on the DPP network
+// (row shifts within 16-lane rows, then row broadcasts), no LDS round trip.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+// LDS writes of this wave are visible to its later LDS reads (a wave's LDS
+// operations complete in order; this stops the compiler from moving reads up)
+__device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 template <int PF, bool LO, bool P9>
 __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict__ imgs,
                                                       const DetItem *__restrict__ items,
@@ -164,47 +199,26 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
                                                       uint32_t *__restrict__ cell_keys,
                                                       uint16_t *__restrict__ crf, DetParams prm) {
     __shared__ __attribute__((aligned(16))) uint32_t tile[FT_ROWS * FT_W];
-    __shared__ uint16_t s_q[FT_Q1];
-    __shared__ uint16_t s_q2[FT_Q2];
+    __shared__ uint16_t s_q[4][FT_QW];
+    __shared__ uint16_t s_q2[4][FT_Q2W];
     __shared__ uint32_t s_hi[FT_MAX_CELLS], s_lo[FT_MAX_CELLS];
     __shared__ uint8_t s_run[FT_MAX_CELLS];
-    __shared__ int s_qcnt[4];
-    __shared__ int s_any, s_n2;
 
     const DetItem it = items[blockIdx.x];
     const ImageDev &im = imgs[it.image];
     const LevelDev lv = im.lv[it.level];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int c = lv.cell;
     const int nk = it.nkx * it.nky;
     const int x0 = it.cx0 * c, y0 = it.cy0 * c;
     const int x1 = min(x0 + it.nkx * c, lv.w), y1 = min(y0 + it.nky * c, lv.h);
     const int tw = x1 - x0, th = y1 - y0;
 
-    // learned gating: which cells of this tile run at all
-    if (tid == 0) {
-        s_any = 0;
-        s_n2 = 0;
-    }
-    __syncthreads();
-    for (int k = tid; k < nk; k += 256) {
-        bool run = true;
-        if (mask) run = mask[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] != 0;
-        s_run[k] = run;
-        s_hi[k] = 0;
-        s_lo[k] = 0;
-        if (run) s_any = 1;
-    }
-    __syncthreads();
-    if (!s_any && !crf) {
-        for (int k = tid; k < nk; k += 256)
-            cell_keys[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] = 0;
-        return;
-    }
-
     // 1. stage rows y0-3 .. y1+2; word column j holds image columns xb + j and
     //    xb + 64 + j.  One task = one 16-byte chunk of both halves of a row, so
-    //    every thread has its two loads in flight at once.
+    //    every thread has its two loads in flight at once.  Cell state is
+    //    cleared meanwhile (learned gating: which cells run at all).
     const uint8_t *src = (it.level == 0 ? images : pyr) + lv.offset;
     const int xb = (x0 - 3) & ~15, delta = (x0 - 3) - xb;
     const bool aligned = it.level > 0 || prm.aligned != 0;
@@ -229,11 +243,31 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
             dst[k] = v;
         }
     }
-    __syncthreads();
+    int my_any = 0;
+    for (int k = tid; k < nk; k += 256) {
+        bool run = true;
+        if (mask) run = mask[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] != 0;
+        s_run[k] = run;
+        s_hi[k] = 0;
+        s_lo[k] = 0;
+        my_any |= run;
+    }
+    if (mask) {
+        if (!__syncthreads_or(my_any) && !crf) {
+            for (int k = tid; k < nk; k += 256)
+                cell_keys[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] = 0;
+            return;
+        }
+    } else {
+        __syncthreads();
+    }
 
-    // 2. prefilter: each lane collects its candidates (rows wave + 4k) in a
-    //    bit mask: bit k = column lane, bit 16 + k = column lane + 64.
-    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    // From here until the cell keys are reduced every wave works alone on
+    // its rows (wave + 4k): its own candidate and survivor queues, no block
+    // barrier.
+    //
+    // 2. prefilter: each lane collects its candidates in a bit mask: bit k =
+    //    column lane of row wave + 4k, bit 16 + k = column lane + 64.
     const int B = prm.border;
     const int gxl = x0 + lane, gxh = x0 + FT_HALF + lane;
     const bool okl = lane < tw && gxl >= B && gxl < lv.w - B;
@@ -271,41 +305,38 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
         cm |= f << k;
     }
     cm &= (okl ? 0xFFu : 0u) | (okh ? 0xFF0000u : 0u);
-    if (mask && cm) {
+    if (mask) {
         // learned gating: pixels of skipped cells never become candidates
+        const int ka = min(kxl, it.nkx - 1), kb = min(kxh, it.nkx - 1);
         uint32_t gm = 0;
+        if (it.nky == 1) {                               // one cell row (levels with c >= 16): per lane
+            gm = (s_run[ka] ? 0xFFu : 0u) | (s_run[kb] ? 0xFF0000u : 0u);
+        } else {
 #pragma unroll
-        for (int k = 0; k < FT_MAX_ROWS / 4; k++) {
-            const int r = wv + 4 * k;
-            if (r >= th) break;                          // uniform
-            const int kb = (r / c) * it.nkx;
-            gm |= (s_run[kb + min(kxl, it.nkx - 1)] ? 1u : 0u) << k;
-            gm |= (s_run[kb + min(kxh, it.nkx - 1)] ? 0x10000u : 0u) << k;
+            for (int k = 0; k < FT_MAX_ROWS / 4; k++) {
+                const int r = wv + 4 * k;
+                if (r >= th) break;                      // uniform
+                const int kr = (r / c) * it.nkx;
+                gm |= (s_run[kr + ka] ? 1u : 0u) << k;
+                gm |= (s_run[kr + kb] ? 0x10000u : 0u) << k;
+            }
         }
         cm &= gm;
     }
 
-    // 3a. candidate queue (entry = row << 7 | column), contiguous over the
-    //     block: a wave scan of the per-lane counts, the waves' totals, then
-    //     every lane writes its own entries
+    // 3a. this wave's candidate queue (entry = row << 7 | column): a DPP scan
+    //     of the per-lane counts places every lane's entries
     const int cnt = __popc(cm);
-    int incl = cnt;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int v = __shfl_up(incl, d);
-        if (lane >= d) incl += v;
-    }
-    if (lane == 63) s_qcnt[wv] = incl;
-    __syncthreads();
-    const int q0 = s_qcnt[0], q1 = s_qcnt[1], q2 = s_qcnt[2], q3 = s_qcnt[3];
-    const int total = q0 + q1 + q2 + q3;
-    int pos = incl - cnt + (wv > 0 ? q0 : 0) + (wv > 1 ? q1 : 0) + (wv > 2 ? q2 : 0);
+    const int incl = wave_incl_scan(cnt);
+    const int qn = __builtin_amdgcn_readlane(incl, 63);
+    uint16_t *const q = s_q[wv];
+    int pos = incl - cnt;
     while (cm) {
         const int bit = __builtin_ctz(cm);
         cm &= cm - 1;
-        s_q[pos++] = (uint16_t)(((wv + 4 * (bit & 15)) << 7) | (lane + FT_HALF * (bit >> 4)));
+        q[pos++] = (uint16_t)(((wv + 4 * (bit & 15)) << 7) | (lane + FT_HALF * (bit >> 4)));
     }
-    __syncthreads();
+    wave_lds_fence();
 
     const uint16_t *t16 = (const uint16_t *)tile;
     // the 16 ring pixels and the centre of tile pixel (r, col), from LDS
@@ -361,8 +392,12 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
     //     threshold is necessary for a corner at either threshold.  Survivors
     //     (entry = cmin << 14 | rd << 13 | rb << 12 | row << 7 | column) go to
     //     a second queue.
-    for (int i = tid; i < total; i += 256) {
-        const int e = s_q[i];
+    uint16_t *const q2 = s_q2[wv];
+    int n2 = 0;                                  // survivors so far (uniform)
+    for (int base = 0; base < qn; base += 64) {
+        const int i = base + lane;
+        const bool act = i < qn;
+        const int e = act ? q[i] : 0;
         const int r = (e >> 7) & 63, col = e & 127;
         int p[16];
         const int ctr = load_ring(r, col, p);
@@ -394,26 +429,22 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
             if (pb) rb = run_ge<false>(ring_mask(p, ctr, prm.eps_min, false), prm.p_min);
             if (pd) rd = run_ge<false>(ring_mask(p, ctr, prm.eps_min, true), prm.p_min);
         }
-        const bool surv = rb || rd;
+        const bool surv = act && (rb || rd);
         const uint64_t bal = __ballot(surv);
-        if (bal) {
-            int wbase = 0;
-            if (lane == __builtin_ffsll((long long)bal) - 1) wbase = atomicAdd(&s_n2, __popcll(bal));
-            wbase = __shfl(wbase, __builtin_ffsll((long long)bal) - 1);
-            const int pos2 = wbase + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-            if (surv) {
-                if (pos2 < FT_Q2)
-                    s_q2[pos2] = (uint16_t)((cmin ? 1 << 14 : 0) | (rd ? 1 << 13 : 0) | (rb ? 1 << 12 : 0) | (r << 7) | col);
-                else
-                    finish(r, col, rb, rd, cmin);      // queue full: decide in place
-            }
+        const int pos2 = n2 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+        if (surv) {
+            if (pos2 < FT_Q2W)
+                q2[pos2] = (uint16_t)((cmin ? 1 << 14 : 0) | (rd ? 1 << 13 : 0) | (rb ? 1 << 12 : 0) | (r << 7) | col);
+            else
+                finish(r, col, rb, rd, cmin);        // queue full: decide in place
         }
+        n2 += __popcll(bal);
     }
-    __syncthreads();
-    // 3c. decide the survivors densely
-    const int ns = min(s_n2, FT_Q2);
-    for (int i = tid; i < ns; i += 256) {
-        const int e = s_q2[i];
+    wave_lds_fence();
+    // 3c. decide this wave's survivors densely, then reduce over the block
+    const int ns = min(n2, FT_Q2W);
+    for (int i = lane; i < ns; i += 64) {
+        const int e = q2[i];
         finish((e >> 7) & 31, e & 127, (e >> 12) & 1, (e >> 13) & 1, (e >> 14) & 1);
     }
     __syncthreads();
