@@ -45,6 +45,11 @@ struct DiscTables {
 };
 __constant__ DiscTables c_disc;
 
+// Each wave works on its own keypoint and its own LDS region, so the waves
+// of a block never wait for one another: a wave's LDS operations complete
+// in order, and this fence keeps the compiler from moving reads up.
+__device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 __device__ __forceinline__ int half_plane(int64_t x, int64_t y) { return (y < 0 || (y == 0 && x < 0)) ? 1 : 0; }
 
 __device__ __forceinline__ uint32_t fetch4c(const uint8_t *row, int x, int w, bool aligned) {
@@ -96,7 +101,7 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
             if (t < 37 * 10) s_r[wave][(t / 10) * (R_STRIDE / 4) + t % 10] = v[u];
         }
     }
-    __syncthreads();
+    wave_lds_fence();
     // intensity centroid: lane v' = v + 15 < 31 sums its disc row
     int m10 = 0, m01 = 0;
     if (active && lane < 31) {
@@ -140,7 +145,7 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         m10 += __shfl_xor(m10, o);
         m01 += __shfl_xor(m01, o);
     }
-    __syncthreads();
+    wave_lds_fence();
     if (active) {
         if (a.blur) {
             // vertical pass on the transposed rows: task (column c, group j) -> rows 4j..4j+3
@@ -174,7 +179,7 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
     }
     const uint64_t gem = __ballot(ge);
     const int bin = (m10 == 0 && m01 == 0) ? 0 : (__popcll(gem) % 30);
-    __syncthreads();
+    wave_lds_fence();
     if (active) {
         const int8_t *pr = pat_rot + (int64_t)bin * 256 * 4;
         uint32_t words[8];

@@ -101,13 +101,15 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
 constexpr int SEL_THREADS = 1024;
 constexpr int SEL_WAVES = SEL_THREADS / 64;
 
-// Exclusive prefix count of `flag` over the block; returns the prefix and
-// sets *total.  Contains two barriers: every thread must call it.
-__device__ __forceinline__ int block_scan(bool flag, int *wave_cnt, int *total) {
+// Exclusive prefix counts of two flags at once (a in the low 16 bits, b in
+// the high 16 bits; chunks hold at most SEL_THREADS cells); *total gets
+// both totals.  Two barriers: every thread must call it.
+__device__ __forceinline__ int block_scan_pair(bool a, bool b, int *wave_cnt, int *total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t bal = __ballot(flag);
-    const int in_wave = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wave_cnt[wave] = __popcll(bal);
+    const uint64_t ba = __ballot(a), bb = __ballot(b);
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int in_wave = __popcll(ba & below) | (__popcll(bb & below) << 16);
+    if (lane == 0) wave_cnt[wave] = __popcll(ba) | (__popcll(bb) << 16);
     __syncthreads();
     int before = 0, all = 0;
     for (int w = 0; w < SEL_WAVES; w++) {
@@ -131,29 +133,29 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
     const int n = (int)im.n_cells;
     const int tid = threadIdx.x;
 
-    int local = 0;
-    for (int i = tid; i < n; i += SEL_THREADS) local += rank[base + i] != 0;
-    // block sum via the histogram array
-    hist[tid] = local;
+    // pass 1: histogram of the high 10 bits of the nonzero ranks (ranks <
+    // 2^20); its total is the number of survivors
+    hist[tid] = 0;
     __syncthreads();
-    for (int s = SEL_THREADS / 2; s > 0; s >>= 1) {
-        if (tid < s) hist[tid] += hist[tid + s];
-        __syncthreads();
+    for (int i = tid; i < n; i += SEL_THREADS) {
+        const uint32_t v = rank[base + i];
+        if (v) atomicAdd(&hist[v >> 10], 1);
     }
-    const int m = hist[0];
     __syncthreads();
+    {
+        const int lane = tid & 63, wave = tid >> 6;
+        int v = hist[tid];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) wave_cnt[wave] = v;
+    }
+    __syncthreads();
+    int m = 0;
+    for (int w = 0; w < SEL_WAVES; w++) m += wave_cnt[w];
 
     uint32_t T = 0;
     int quota = 0;
     if (m > n_max) {
-        // pass 1: bucket of the n_max-th largest rank by its high 10 bits (ranks < 2^20)
-        hist[tid] = 0;
-        __syncthreads();
-        for (int i = tid; i < n; i += SEL_THREADS) {
-            const uint32_t v = rank[base + i];
-            if (v) atomicAdd(&hist[v >> 10], 1);
-        }
-        __syncthreads();
+        // bucket of the n_max-th largest rank, then its low 10 bits
         if (tid == 0) {
             int acc = 0;
             for (int bkt = 1023; bkt >= 0; bkt--) {
@@ -190,16 +192,20 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
         quota = n_max - s_sel[1];
     }
 
-    // compaction in canonical order
-    int running = 0, eq_running = 0;
+    // compaction in canonical order: one block scan per chunk counts, before
+    // each cell, the ranks above T (low 16 bits) and equal to T (high 16
+    // bits); a cell's slot is (# above) + min(# equal, quota)
+    int gt_running = 0, eq_running = 0;
     for (int start = 0; start < n; start += SEL_THREADS) {
         const int i = start + tid;
         const uint32_t v = i < n ? rank[base + i] : 0u;
-        int eq_total, keep_total;
-        const bool is_eq = v != 0 && T != 0 && v == T;
-        const int eq_before = block_scan(is_eq, wave_cnt, &eq_total) + eq_running;
-        const bool keep = v != 0 && (v > T || (is_eq && eq_before < quota));
-        const int slot = block_scan(keep, wave_cnt, &keep_total) + running;
+        const bool gt = v != 0 && v > T;
+        const bool eq = v != 0 && T != 0 && v == T;
+        int tot;
+        const int before = block_scan_pair(gt, eq, wave_cnt, &tot);
+        const int gt_before = gt_running + (before & 0xFFFF), eq_before = eq_running + (before >> 16);
+        const bool keep = gt || (eq && eq_before < quota);
+        const int slot = gt_before + min(eq_before, quota);
         if (keep) {
             int l = 0;
             while (l + 1 < im.n_levels && im.lv[l + 1].cell_offset - base <= i) l++;
@@ -225,10 +231,11 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
                 atomicOr(status, VSFE_DEV_OVERFLOW);
             }
         }
-        running += keep_total;
-        eq_running += eq_total;
+        gt_running += tot & 0xFFFF;
+        eq_running += tot >> 16;
     }
-    if (tid == 0) kp_count[blockIdx.x] = running < n_max ? running : n_max;
+    const int kept = gt_running + min(eq_running, quota);
+    if (tid == 0) kp_count[blockIdx.x] = kept < n_max ? kept : n_max;
 }
 
 }  // namespace vsfe
