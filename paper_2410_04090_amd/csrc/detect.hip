@@ -203,6 +203,7 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
     __shared__ uint16_t s_q2[4][FT_Q2W];
     __shared__ uint32_t s_hi[FT_MAX_CELLS], s_lo[FT_MAX_CELLS];
     __shared__ uint8_t s_run[FT_MAX_CELLS];
+    __shared__ int s_anyw[4];
 
     const DetItem it = items[blockIdx.x];
     const ImageDev &im = imgs[it.image];
@@ -253,7 +254,11 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
         my_any |= run;
     }
     if (mask) {
-        if (!__syncthreads_or(my_any) && !crf) {
+        // does any cell of the tile run: one flag per wave, one barrier
+        const bool wave_any = __ballot(my_any) != 0;
+        if (lane == 0) s_anyw[wave] = wave_any;
+        __syncthreads();
+        if (!(s_anyw[0] | s_anyw[1] | s_anyw[2] | s_anyw[3]) && !crf) {
             for (int k = tid; k < nk; k += 256)
                 cell_keys[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] = 0;
             return;

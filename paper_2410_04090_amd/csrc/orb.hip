@@ -13,9 +13,11 @@
 //    a ballot counts them (bin = count mod 30, 0 for m = 0);
 //  * smoothing only of the 31 x 31 patch the tests can touch, separable
 //    7-tap [18 33 49 56 49 33 18] / 256 with each pass rounded half up;
-//    every output is two dot4 ops over an alignbyte window; the horizontal
-//    pass writes its result transposed so the vertical pass is again a
-//    contiguous dot product, and the final patch is stored transposed;
+//    both passes are exact integer products with a banded weight matrix on
+//    v_mfma_i32_16x16x32_i8 (pixels offset by -128 to fit signed bytes, the
+//    offset added back as 128 * 256 before rounding); the horizontal pass
+//    writes its result transposed so the vertical pass reads 8 rows of one
+//    column per lane, and the final patch is stored transposed;
 //  * 256 tests on the bin-rotated pattern (precomputed per bin in the
 //    context), 64 per ballot, written as 8 words.
 // The whole-level smoothed pyramid never touches HBM.
@@ -27,8 +29,11 @@ namespace vsfe {
 
 constexpr int ORB_WAVES = 4;
 constexpr int R_STRIDE = 40;      // staged 37 x 37 neighbourhood, one row per 40 bytes
-constexpr int HT_STRIDE = 40;     // horizontal pass, transposed: [column][row], 37 rows used
+constexpr int R_BYTES = 48 * R_STRIDE + 32;   // 48 rows (3 MFMA row tiles) + read slack
+constexpr int HT_STRIDE = 48;     // horizontal pass, transposed: [column][row], 37 of 48 rows used
+constexpr int HT_BYTES = 32 * HT_STRIDE + 16;
 constexpr int B_STRIDE = 32;      // final smoothed patch, transposed: [column][row], 31 used
+constexpr int B_BYTES = 32 * B_STRIDE;
 constexpr uint32_t W_LO = 18u | (33u << 8) | (49u << 16) | (56u << 24);
 constexpr uint32_t W_HI = 49u | (33u << 8) | (18u << 16);
 
@@ -44,6 +49,20 @@ struct DiscTables {
     uint32_t ramp[31][8];
 };
 __constant__ DiscTables c_disc;
+
+// Constant MFMA operands of the smoothing (v_mfma_i32_16x16x32_i8, 8 bytes
+// per lane: lane l covers K = 8 (l / 16) .. + 7 of row / column l % 16):
+//  hb[kc][nt][l]: horizontal pass B = K0[j][c] = w[j - c] (j = 32 kc + 8 (l/16) + b,
+//                 c = 16 nt + l % 16), zero outside 0 <= j - c <= 6;
+//  va[kc][mt][l]: vertical pass A = Kv[r'][r] = w[r - r'] (r' = 16 mt + l % 16,
+//                 r = 32 kc + 8 (l/16) + b).
+struct SmoothTables {
+    uint64_t hb[2][2][64];
+    uint64_t va[2][2][64];
+};
+__constant__ SmoothTables c_smooth;
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // Each wave works on its own keypoint and its own LDS region, so the waves
 // of a block never wait for one another: a wave's LDS operations complete
@@ -65,9 +84,9 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
                                                   const int32_t *__restrict__ kp_count,
                                                   const int8_t *__restrict__ pat_rot, uint32_t *__restrict__ desc,
                                                   OrbArgs a) {
-    __shared__ __attribute__((aligned(16))) uint32_t s_r[ORB_WAVES][37 * R_STRIDE / 4 + 1];
-    __shared__ __attribute__((aligned(16))) uint32_t s_ht[ORB_WAVES][31 * HT_STRIDE / 4 + 1];
-    __shared__ __attribute__((aligned(16))) uint32_t s_b[ORB_WAVES][31 * B_STRIDE / 4];
+    __shared__ __attribute__((aligned(16))) uint32_t s_r[ORB_WAVES][R_BYTES / 4];
+    __shared__ __attribute__((aligned(16))) uint32_t s_ht[ORB_WAVES][HT_BYTES / 4];
+    __shared__ __attribute__((aligned(16))) uint32_t s_b[ORB_WAVES][B_BYTES / 4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t slot = (int64_t)blockIdx.x * ORB_WAVES + wave;
     const int image = (int)(slot / a.n_max);
@@ -120,23 +139,37 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         m10 = (int)T - 16 * (int)S;
         m01 = (lane - 15) * (int)S;
     }
+    const int mrow = lane & 15, grp = lane >> 4;
     if (active && a.blur) {
-        // horizontal pass: task (row r, group j) -> outputs at columns 4j..4j+3
-        for (int t = lane; t < 37 * 8; t += 64) {
-            const int r = t >> 3, j = t & 7;
-            const uint32_t *w = (const uint32_t *)(R + r * R_STRIDE + 4 * j);
-            const uint32_t d0 = w[0], d1 = w[1], d2 = w[2], d3 = w[3];
-            const uint32_t W0 = __builtin_amdgcn_alignbyte(d1, d0, delta);
-            const uint32_t W1 = __builtin_amdgcn_alignbyte(d2, d1, delta);
-            const uint32_t W2 = __builtin_amdgcn_alignbyte(d3, d2, delta);
+        // horizontal pass on MFMA: H[r][c] = sum_j R'[r][j] K0[j][c] with
+        // R'[r][j] = R[r][j + delta] - 128 (signed bytes), so the rounded
+        // output is (acc + 128 * 256 + 128) >> 8; 3 row tiles x 2 column
+        // tiles x 2 K chunks.  Written transposed, 4 rows per dword.
+        uint64_t bh[2][2];
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const int c = 4 * j + k;
-                if (c >= 31) break;
-                const uint32_t lo = __builtin_amdgcn_alignbyte(W1, W0, k);
-                const uint32_t hi = __builtin_amdgcn_alignbyte(W2, W1, k);
-                const uint32_t s = __builtin_amdgcn_udot4(lo, W_LO, __builtin_amdgcn_udot4(hi, W_HI, 128u, false), false);
-                HT[c * HT_STRIDE + r] = (uint8_t)(s >> 8);
+        for (int kc = 0; kc < 2; kc++)
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++) bh[kc][nt] = c_smooth.hb[kc][nt][lane];
+#pragma unroll
+        for (int mt = 0; mt < 3; mt++) {
+            i32x4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+            for (int kc = 0; kc < 2; kc++) {
+                const uint32_t *w = (const uint32_t *)(R + (16 * mt + mrow) * R_STRIDE + 32 * kc + 8 * grp);
+                const uint32_t d0 = w[0], d1 = w[1], d2 = w[2];
+                const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, delta) ^ 0x80808080u;
+                const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, delta) ^ 0x80808080u;
+                const long av = (long)(((uint64_t)hi << 32) | lo);
+#pragma unroll
+                for (int nt = 0; nt < 2; nt++)
+                    acc[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8(av, (long)bh[kc][nt], acc[nt], 0, 0, 0);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++) {
+                uint32_t word = 0;
+#pragma unroll
+                for (int r = 0; r < 4; r++) word |= (uint32_t)((acc[nt][r] + 32896) >> 8) << (8 * r);
+                *(uint32_t *)(HT + (16 * nt + mrow) * HT_STRIDE + 16 * mt + 4 * grp) = word;
             }
         }
     }
@@ -148,20 +181,29 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
     wave_lds_fence();
     if (active) {
         if (a.blur) {
-            // vertical pass on the transposed rows: task (column c, group j) -> rows 4j..4j+3
-            for (int t = lane; t < 31 * 8; t += 64) {
-                const int c = t >> 3, j = t & 7;
-                const uint32_t *w = (const uint32_t *)(HT + c * HT_STRIDE + 4 * j);
-                const uint32_t W0 = w[0], W1 = w[1], W2 = w[2];
-                uint32_t word = 0;
+            // vertical pass on MFMA: V[r'][c] = sum_r Kv[r'][r] (H[r][c] - 128),
+            // B read from the transposed H (8 rows of one column per lane);
+            // the output is written transposed, 4 rows per dword
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const uint32_t lo = __builtin_amdgcn_alignbyte(W1, W0, k);
-                    const uint32_t hi = __builtin_amdgcn_alignbyte(W2, W1, k);
-                    const uint32_t s = __builtin_amdgcn_udot4(lo, W_LO, __builtin_amdgcn_udot4(hi, W_HI, 128u, false), false);
-                    word |= (s >> 8) << (8 * k);
+            for (int mt = 0; mt < 2; mt++) {
+                i32x4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+                for (int kc = 0; kc < 2; kc++) {
+                    const long av = (long)c_smooth.va[kc][mt][lane];
+#pragma unroll
+                    for (int nt = 0; nt < 2; nt++) {
+                        const uint2 hv = *(const uint2 *)(HT + (16 * nt + mrow) * HT_STRIDE + 32 * kc + 8 * grp);
+                        const long bv = (long)((((uint64_t)(hv.y ^ 0x80808080u)) << 32) | (hv.x ^ 0x80808080u));
+                        acc[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8(av, bv, acc[nt], 0, 0, 0);
+                    }
                 }
-                s_b[wave][(c * B_STRIDE + 4 * j) >> 2] = word;
+#pragma unroll
+                for (int nt = 0; nt < 2; nt++) {
+                    uint32_t word = 0;
+#pragma unroll
+                    for (int r = 0; r < 4; r++) word |= (uint32_t)((acc[nt][r] + 32896) >> 8) << (8 * r);
+                    s_b[wave][((16 * nt + mrow) * B_STRIDE + 16 * mt + 4 * grp) >> 2] = word;
+                }
             }
         } else {
             for (int t = lane; t < 31 * 31; t += 64) {
@@ -222,6 +264,25 @@ static int32_t upload_disc(int device, hipStream_t st) {
     (void)st;
     if (hipMemcpyToSymbol(HIP_SYMBOL(c_disc), &t, sizeof(t), 0, hipMemcpyHostToDevice) != hipSuccess)
         return fail(VSFE_EHIP, "upload of the disc tables failed");
+    static const int kw[7] = {18, 33, 49, 56, 49, 33, 18};
+    SmoothTables sm;
+    memset(&sm, 0, sizeof(sm));
+    for (int kc = 0; kc < 2; kc++)
+        for (int t2 = 0; t2 < 2; t2++)
+            for (int l = 0; l < 64; l++) {
+                uint64_t hb = 0, va = 0;
+                for (int bb = 0; bb < 8; bb++) {
+                    const int k = 32 * kc + 8 * (l >> 4) + bb;
+                    const int dh = k - (16 * t2 + (l & 15));     // j - c
+                    const int dv = k - (16 * t2 + (l & 15));     // r - r'
+                    if (dh >= 0 && dh <= 6) hb |= (uint64_t)kw[dh] << (8 * bb);
+                    if (dv >= 0 && dv <= 6) va |= (uint64_t)kw[dv] << (8 * bb);
+                }
+                sm.hb[kc][t2][l] = hb;
+                sm.va[kc][t2][l] = va;
+            }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_smooth), &sm, sizeof(sm), 0, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(VSFE_EHIP, "upload of the smoothing tables failed");
     if (device >= 0 && device < 64) g_disc_ready[device] = true;
     return VSFE_OK;
 }
