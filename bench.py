@@ -344,6 +344,7 @@ def main():
         "path_alg_bytes": int(path_bytes),
         "path_hbm_frac": round(path_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "keypoints_per_image": round(n_kp / len(sizes), 1),
+        "fast_br_grid_threads": int(vsfe.batch_info(fe.batch).n_det_items) * 256,
     }
     if tune is not None:
         res["autotune"] = tune

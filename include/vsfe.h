@@ -103,6 +103,9 @@ typedef struct vsfe_batch_info {
     int64_t match_capacity;   /* stereo outputs = n_pairs * n_max              */
     int32_t n_images;
     int32_t n_levels;
+    int32_t n_det_items;      /* detector work items (256-thread blocks) with the
+                                 batch's current tiles                          */
+    int32_t reserved;
 } vsfe_batch_info;
 
 typedef struct vsfe_level_info {

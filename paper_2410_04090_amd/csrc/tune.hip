@@ -44,6 +44,7 @@ void det_items_build(vsfe_batch *b) {
     }
     b->det_start[L] = (int32_t)b->h_det_items.size();
     b->n_det_items = (int32_t)b->h_det_items.size();
+    b->info.n_det_items = b->n_det_items;
 }
 
 static bool tile_ok(int tw, int th) { return tw >= 8 && tw <= 128 && th >= 8 && th <= 32; }

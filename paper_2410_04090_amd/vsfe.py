@@ -46,7 +46,8 @@ class BatchInfo(C.Structure):
     _fields_ = [("input_bytes", C.c_int64), ("pyr_bytes", C.c_int64), ("crf_elems", C.c_int64),
                 ("n_cells", C.c_int64), ("n_cells0", C.c_int64), ("kp_capacity", C.c_int64),
                 ("workspace_bytes", C.c_int64), ("match_capacity", C.c_int64),
-                ("n_images", C.c_int32), ("n_levels", C.c_int32)]
+                ("n_images", C.c_int32), ("n_levels", C.c_int32), ("n_det_items", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class LevelInfo(C.Structure):
