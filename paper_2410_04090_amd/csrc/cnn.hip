@@ -281,9 +281,10 @@ __global__ __launch_bounds__(256) void cnn_fused_fwd_kernel(const CnnImg *__rest
     uint16_t *const s_c2 = s_u;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m = lane & 15, grp = lane >> 4;
-    const int i = find_image(pre_tiles, n, blockIdx.x);
+    const int bt = xcd_item(blockIdx.x, gridDim.x);
+    const int i = find_image(pre_tiles, n, bt);
     const CnnImg im = imgs[i];
-    const int lt = (int)blockIdx.x - pre_tiles[i];
+    const int lt = bt - pre_tiles[i];
     const int ntx = (im.w4 + CF3W - 1) / CF3W;
     const int Y3 = (lt / ntx) * CF3H, X3 = (lt % ntx) * CF3W;
     const int Y2 = 2 * Y3 - 1, X2 = 2 * X3 - 1, Y1 = 2 * Y2 - 1, X1 = 2 * X2 - 1, Y0 = 2 * Y1 - 1, X0 = 2 * X1 - 1;

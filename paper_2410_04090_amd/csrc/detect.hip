@@ -205,6 +205,8 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
     __shared__ uint8_t s_run[FT_MAX_CELLS];
     __shared__ int s_anyw[4];
 
+    // level-major items in dispatch order: each level spreads over all XCDs
+    // (a contiguous range per XCD would give some XCDs only the heavy level 0)
     const DetItem it = items[blockIdx.x];
     const ImageDev &im = imgs[it.image];
     const LevelDev lv = im.lv[it.level];

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
     __shared__ __attribute__((aligned(16))) uint32_t s_ht[ORB_WAVES][HT_BYTES / 4];
     __shared__ __attribute__((aligned(16))) uint32_t s_b[ORB_WAVES][B_BYTES / 4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t slot = (int64_t)blockIdx.x * ORB_WAVES + wave;
+    const int64_t slot = (int64_t)xcd_item(blockIdx.x, gridDim.x) * ORB_WAVES + wave;
     const int image = (int)(slot / a.n_max);
     const int i = (int)(slot - (int64_t)image * a.n_max);
     const bool active = image < a.n_images && i < kp_count[image];

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
                                                        const uint32_t *__restrict__ cell_keys,
                                                        uint32_t *__restrict__ rank, int pfa, int nms_mode) {
     constexpr int Q = 2 * R + 1, NS = Q * Q, CENTER = R * Q + R;
-    const CellChunk ch = chunks[blockIdx.x];
+    const CellChunk ch = chunks[xcd_item(blockIdx.x, gridDim.x)];
     const ImageDev &im = imgs[ch.image];
     const LevelDev lv = im.lv[ch.level];
     const int idx = (int)ch.first + (int)threadIdx.x;

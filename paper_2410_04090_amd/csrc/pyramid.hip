@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
                                                             const uint8_t *__restrict__ images,
                                                             uint8_t *__restrict__ pyr, int aligned0) {
     __shared__ __attribute__((aligned(16))) uint32_t s_src[PYR_SH * (PYR_LDS_W / 4)];
-    const PyrItem it = items[blockIdx.x];
+    const PyrItem it = items[xcd_item(blockIdx.x, gridDim.x)];
     const LevelDev s = imgs[it.image].lv[level - 1];
     const LevelDev d = imgs[it.image].lv[level];
     const uint8_t *src = (level == 1 ? images : pyr) + s.offset;

@@ -106,6 +106,18 @@ struct vsfe_batch {
 
 namespace vsfe {
 
+// XCD-aware block order.  Workgroups are dispatched round-robin over the 8
+// XCDs (block b runs on XCD b % 8), each with its own L2; this maps block b
+// to work item index so that each XCD gets a contiguous range of items
+// (neighbouring tiles share halo rows and cache lines in one L2).  A
+// bijection on [0, n).
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_item(int b, int n) {
+    const int q = n / N_XCD, r = n % N_XCD;
+    const int x = b % N_XCD, k = b / N_XCD;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 void set_error(const std::string &msg);
 int32_t fail(int32_t code, const std::string &msg);
 int32_t check_launch(const char *what);
