@@ -303,13 +303,14 @@ def main():
 
     # ---- algorithmic bytes: per call, whole batch
     L = wl.params.n_levels
-    px_all = px_up = px_last = 0
+    px_all = px_up = px_last = sum_l0 = 0
     n_cells = int(fe.info.n_cells)
     for (w, h) in sizes:
         ls = level_sizes(w, h, L)
         px_all += sum(a * bb for a, bb in ls)
         px_up += sum(a * bb for a, bb in ls[1:])
         px_last += ls[-1][0] * ls[-1][1]
+        sum_l0 += w * h
     n_kp = int(fe.kp_count.sum().item())
     n_left = int(sum(fe.kp_count[0::2].tolist()))
     alg = {
@@ -331,7 +332,10 @@ def main():
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "alg_bytes_per_launch": int(alg[dominant]), "avg_launch_us": round(call_us[dominant], 2),
             "source_sha": source_sha(dominant)}
-    path_bytes = sum(alg.values())
+    # whole-path algorithmic bytes: level 0 read once, every other level
+    # written once and read once, keypoints (16 B) and descriptors (32 B)
+    # written, matches (8 B per left keypoint) written
+    path_bytes = sum_l0 + 2 * px_up + 48 * n_kp + 8 * n_left
     res = {
         "metric": METRIC, "value": round(value, 1), "unit": "stereo pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -343,6 +347,7 @@ def main():
         "calls_us": {k: round(v, 2) for k, v in call_us.items()},
         "path_alg_bytes": int(path_bytes),
         "path_hbm_frac": round(path_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "calls_alg_bytes": int(sum(alg.values())),
         "keypoints_per_image": round(n_kp / len(sizes), 1),
         "fast_br_grid_threads": int(vsfe.batch_info(fe.batch).n_det_items) * 256,
     }

@@ -225,6 +225,14 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
     const uint8_t *src = (it.level == 0 ? images : pyr) + lv.offset;
     const int xb = (x0 - 3) & ~15, delta = (x0 - 3) - xb;
     const bool aligned = it.level > 0 || prm.aligned != 0;
+    // run flags of cells tid and tid + 256, loaded together with the rows
+    // (one memory round trip)
+    uint32_t mf0 = 1u, mf1 = 1u;
+    if (mask) {
+        const int k0 = tid, k1 = tid + 256;
+        mf0 = k0 < nk ? mask[lv.cell_offset + (int64_t)(it.cy0 + k0 / it.nkx) * lv.ncx + (it.cx0 + k0 % it.nkx)] : 0u;
+        mf1 = k1 < nk ? mask[lv.cell_offset + (int64_t)(it.cy0 + k1 / it.nkx) * lv.ncx + (it.cx0 + k1 % it.nkx)] : 0u;
+    }
     if (tid < (th + 6) * FT_CHUNKS) {
         const int rr = tid / FT_CHUNKS, m = tid - rr * FT_CHUNKS;
         const int gy = y0 - 3 + rr;
@@ -247,13 +255,16 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
         }
     }
     int my_any = 0;
-    for (int k = tid; k < nk; k += 256) {
-        bool run = true;
-        if (mask) run = mask[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] != 0;
-        s_run[k] = run;
-        s_hi[k] = 0;
-        s_lo[k] = 0;
-        my_any |= run;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int k = tid + 256 * h;
+        if (k < nk) {
+            const bool run = (h ? mf1 : mf0) != 0u;
+            s_run[k] = run;
+            s_hi[k] = 0;
+            s_lo[k] = 0;
+            my_any |= run;
+        }
     }
     if (mask) {
         // does any cell of the tile run: one flag per wave, one barrier
