@@ -44,9 +44,8 @@ constexpr int FT_CHUNKS = 6;                     // 16-byte source chunks per ro
 constexpr int FT_W = 100;
 constexpr int FT_MAX_ROWS = 32;
 constexpr int FT_ROWS = FT_MAX_ROWS + 6;
-constexpr int FT_MAX_CELLS = 512;
+constexpr int FT_MAX_CELLS = 256;               // at most 32 x 8 cells per tile
 constexpr int FT_QW = (FT_MAX_ROWS / 4) * 2 * FT_HALF;   // one wave's candidates (all of its pixels)
-constexpr int FT_Q2W = 512;                               // one wave's survivors (overflow decided inline)
 
 struct DetParams {
     int eps_hi, eps_lo, p_min, p_max, border, eps_min, aligned;
@@ -191,7 +190,7 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 __device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 template <int PF, bool LO, bool P9>
-__global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict__ imgs,
+__global__ __launch_bounds__(256, 6) void fast_br_kernel(const ImageDev *__restrict__ imgs,
                                                       const DetItem *__restrict__ items,
                                                       const uint8_t *__restrict__ images,
                                                       const uint8_t *__restrict__ pyr,
@@ -200,7 +199,6 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
                                                       uint16_t *__restrict__ crf, DetParams prm) {
     __shared__ __attribute__((aligned(16))) uint32_t tile[FT_ROWS * FT_W];
     __shared__ uint16_t s_q[4][FT_QW];
-    __shared__ uint16_t s_q2[4][FT_Q2W];
     __shared__ uint32_t s_hi[FT_MAX_CELLS], s_lo[FT_MAX_CELLS];
     __shared__ uint8_t s_run[FT_MAX_CELLS];
     __shared__ int s_anyw[4];
@@ -410,7 +408,10 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
     //     threshold is necessary for a corner at either threshold.  Survivors
     //     (entry = cmin << 14 | rd << 13 | rb << 12 | row << 7 | column) go to
     //     a second queue.
-    uint16_t *const q2 = s_q2[wv];
+    // survivors are compacted in place: after the iteration that reads
+    // entries [base, base + 64), at most base + 64 survivors exist, so a
+    // survivor never overwrites an entry that is still to be read
+    uint16_t *const q2 = q;
     int n2 = 0;                                  // survivors so far (uniform)
     for (int base = 0; base < qn; base += 64) {
         const int i = base + lane;
@@ -451,16 +452,13 @@ __global__ __launch_bounds__(256) void fast_br_kernel(const ImageDev *__restrict
         const uint64_t bal = __ballot(surv);
         const int pos2 = n2 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
         if (surv) {
-            if (pos2 < FT_Q2W)
-                q2[pos2] = (uint16_t)((cmin ? 1 << 14 : 0) | (rd ? 1 << 13 : 0) | (rb ? 1 << 12 : 0) | (r << 7) | col);
-            else
-                finish(r, col, rb, rd, cmin);        // queue full: decide in place
+            q2[pos2] = (uint16_t)((cmin ? 1 << 14 : 0) | (rd ? 1 << 13 : 0) | (rb ? 1 << 12 : 0) | (r << 7) | col);
         }
         n2 += __popcll(bal);
     }
     wave_lds_fence();
     // 3c. decide this wave's survivors densely, then reduce over the block
-    const int ns = min(n2, FT_Q2W);
+    const int ns = n2;
     for (int i = lane; i < ns; i += 64) {
         const int e = q2[i];
         finish((e >> 7) & 31, e & 127, (e >> 12) & 1, (e >> 13) & 1, (e >> 14) & 1);

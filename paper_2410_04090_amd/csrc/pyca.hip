@@ -31,7 +31,11 @@ __device__ __forceinline__ bool better(int kl_h, int kr_h, int kl_g, int kr_g, i
     return kl_h > kl_g && kr_h > kr_g;
 }
 
-template <int R>
+// FIX2: the host has checked that at every level the window touches at most
+// 2 x 2 cells, so all candidate keys are loaded up front (all levels' loads
+// in flight together) and then accumulated; otherwise cells are visited in
+// a loop per level.
+template <int R, bool FIX2>
 __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restrict__ imgs,
                                                        const CellChunk *__restrict__ chunks,
                                                        const uint32_t *__restrict__ cell_keys,
@@ -60,8 +64,8 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
     int kl[NS], kr[NS];
 #pragma unroll
     for (int s = 0; s < NS; s++) kl[s] = kr[s] = 0;
-    for (int m = 0; m < im.n_levels; m++) {
-        const LevelDev L = im.lv[m];
+    // candidate cells of level m: those whose pixels can project into the window
+    auto window = [&](const LevelDev &L, int *a0, int *a1, int *b0, int *b1) {
         const float inv = 65536.0f / (float)L.scale_q16;
         int xlo = (int)floorf(((float)(px - R) - 0.5f) * inv) - 1, xhi = (int)floorf(((float)(px + R) + 0.5f) * inv) + 1;
         int ylo = (int)floorf(((float)(py - R) - 0.5f) * inv) - 1, yhi = (int)floorf(((float)(py + R) + 0.5f) * inv) + 1;
@@ -69,26 +73,69 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
         ylo = max(ylo, 0);
         xhi = min(xhi, L.w - 1);
         yhi = min(yhi, L.h - 1);
-        if (xlo > xhi || ylo > yhi) continue;
+        if (xlo > xhi || ylo > yhi) return false;
+        *a0 = xlo / L.cell;
+        *a1 = xhi / L.cell;
+        *b0 = ylo / L.cell;
+        *b1 = yhi / L.cell;
+        return true;
+    };
+    auto add = [&](const LevelDev &L, int aa, int bb, uint32_t k) {
+        if (!k) return;
         const int cm = L.cell;
-        const int a0 = xlo / cm, a1 = xhi / cm, b0 = ylo / cm, b1 = yhi / cm;
-        for (int bb = b0; bb <= b1; bb++)
-            for (int aa = a0; aa <= a1; aa++) {
-                const uint32_t k = cell_keys[L.cell_offset + (int64_t)bb * L.ncx + aa];
-                if (!k) continue;
-                const int o = 1023 - (int)(k & 1023u);
-                const int qx = project_q16(aa * cm + o % cm, L.scale_q16, im.w) - px;
-                const int qy = project_q16(bb * cm + o / cm, L.scale_q16, im.h) - py;
-                if (qx < -R || qx > R || qy < -R || qy > R) continue;
-                const int slot = (qy + R) * Q + (qx + R);
-                const int sc = (int)((k >> 10) & 0xFFFu);
+        const int o = 1023 - (int)(k & 1023u);
+        const int qx = project_q16(aa * cm + o % cm, L.scale_q16, im.w) - px;
+        const int qy = project_q16(bb * cm + o / cm, L.scale_q16, im.h) - py;
+        if (qx < -R || qx > R || qy < -R || qy > R) return;
+        const int slot = (qy + R) * Q + (qx + R);
+        const int sc = (int)((k >> 10) & 0xFFFu);
 #pragma unroll
-                for (int s = 0; s < NS; s++)
-                    if (s == slot) {
-                        kl[s] += 1;
-                        kr[s] += sc;
-                    }
+        for (int s = 0; s < NS; s++)
+            if (s == slot) {
+                kl[s] += 1;
+                kr[s] += sc;
             }
+    };
+    if constexpr (FIX2) {
+        uint32_t kk[VSFE_MAX_LEVELS][4];
+        int ca[VSFE_MAX_LEVELS], cb[VSFE_MAX_LEVELS];
+#pragma unroll
+        for (int m = 0; m < VSFE_MAX_LEVELS; m++) {
+            kk[m][0] = kk[m][1] = kk[m][2] = kk[m][3] = 0u;
+            ca[m] = cb[m] = 0;
+            if (m < im.n_levels) {
+                const LevelDev L = im.lv[m];
+                int a0, a1, b0, b1;
+                if (window(L, &a0, &a1, &b0, &b1)) {
+                    ca[m] = a0;
+                    cb[m] = b0;
+                    const uint32_t *row0 = cell_keys + L.cell_offset + (int64_t)b0 * L.ncx;
+                    const bool ax = a0 + 1 < L.ncx, by = b0 + 1 < L.ncy;
+                    kk[m][0] = row0[a0];
+                    if (ax) kk[m][1] = row0[a0 + 1];
+                    if (by) kk[m][2] = row0[L.ncx + a0];
+                    if (ax && by) kk[m][3] = row0[L.ncx + a0 + 1];
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < VSFE_MAX_LEVELS; m++) {
+            if (m < im.n_levels) {
+                const LevelDev L = im.lv[m];
+#pragma unroll
+                for (int q = 0; q < 4; q++) add(L, ca[m] + (q & 1), cb[m] + (q >> 1), kk[m][q]);
+            }
+        }
+    } else {
+        for (int m = 0; m < im.n_levels; m++) {
+            const LevelDev L = im.lv[m];
+            int a0, a1, b0, b1;
+            if (!window(L, &a0, &a1, &b0, &b1)) continue;
+            a1 = min(a1, L.ncx - 1);
+            b1 = min(b1, L.ncy - 1);
+            for (int bb = b0; bb <= b1; bb++)
+                for (int aa = a0; aa <= a1; aa++) add(L, aa, bb, cell_keys[L.cell_offset + (int64_t)bb * L.ncx + aa]);
+        }
     }
     const int kl_own = kl[CENTER], kr_own = kr[CENTER];
     bool sup = false;
@@ -120,6 +167,34 @@ __device__ __forceinline__ int block_scan_pair(bool a, bool b, int *wave_cnt, in
     __syncthreads();
     *total = all;
     return before + in_wave;
+}
+
+// Over the 1024 buckets of hist, from the top: the bucket where the running
+// count (starting at base) first reaches need.  Thread t takes bucket
+// 1023 - t; a block scan of the counts finds the crossing thread.  Writes
+// the bucket to s_sel[slot_bkt] and the count above it to s_sel[slot_acc].
+// Every thread must call it (two barriers).
+__device__ __forceinline__ void find_bucket(const int *hist, int base, int need, int *wave_cnt, int *s_sel,
+                                            int slot_bkt, int slot_acc) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = hist[1023 - tid];
+    int incl = h;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    if (lane == 63) wave_cnt[wave] = incl;
+    __syncthreads();
+    int before = base;
+    for (int w = 0; w < wave; w++) before += wave_cnt[w];
+    incl += before;
+    // the crossing thread: running count before it < need <= running count with it
+    if (incl >= need && incl - h < need) {
+        s_sel[slot_bkt] = 1023 - tid;
+        s_sel[slot_acc] = incl - h;
+    }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
@@ -156,18 +231,7 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
     int quota = 0;
     if (m > n_max) {
         // bucket of the n_max-th largest rank, then its low 10 bits
-        if (tid == 0) {
-            int acc = 0;
-            for (int bkt = 1023; bkt >= 0; bkt--) {
-                if (acc + hist[bkt] >= n_max) {
-                    s_sel[2] = bkt;
-                    s_sel[1] = acc;
-                    break;
-                }
-                acc += hist[bkt];
-            }
-        }
-        __syncthreads();
+        find_bucket(hist, 0, n_max, wave_cnt, s_sel, 2, 1);
         const int bucket = s_sel[2];
         hist[tid] = 0;
         __syncthreads();
@@ -176,19 +240,8 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
             if (v && (int)(v >> 10) == bucket) atomicAdd(&hist[v & 1023u], 1);
         }
         __syncthreads();
-        if (tid == 0) {
-            int acc = s_sel[1];
-            for (int bkt = 1023; bkt >= 0; bkt--) {
-                if (acc + hist[bkt] >= n_max) {
-                    s_sel[0] = (bucket << 10) | bkt;
-                    s_sel[1] = acc;
-                    break;
-                }
-                acc += hist[bkt];
-            }
-        }
-        __syncthreads();
-        T = (uint32_t)s_sel[0];
+        find_bucket(hist, s_sel[1], n_max, wave_cnt, s_sel, 0, 1);
+        T = (uint32_t)((bucket << 10) | s_sel[0]);
         quota = n_max - s_sel[1];
     }
 
@@ -255,24 +308,28 @@ extern "C" int32_t pyca_cull_aggregate(const vsfe_ctx *ctx, const vsfe_batch *b,
     hipStream_t st = (hipStream_t)stream;
     uint32_t *rank = (uint32_t *)workspace;
     if (b->n_chunks > 0) {
-        switch (p.nms_radius) {
-            case 0:
-                hipLaunchKernelGGL(pfa_eval_kernel<0>, dim3(b->n_chunks), dim3(256), 0, st, b->d_images, b->d_chunks,
-                                   cell_keys, rank, p.pfa, p.nms_mode);
-                break;
-            case 1:
-                hipLaunchKernelGGL(pfa_eval_kernel<1>, dim3(b->n_chunks), dim3(256), 0, st, b->d_images, b->d_chunks,
-                                   cell_keys, rank, p.pfa, p.nms_mode);
-                break;
-            case 2:
-                hipLaunchKernelGGL(pfa_eval_kernel<2>, dim3(b->n_chunks), dim3(256), 0, st, b->d_images, b->d_chunks,
-                                   cell_keys, rank, p.pfa, p.nms_mode);
-                break;
-            default:
-                hipLaunchKernelGGL(pfa_eval_kernel<3>, dim3(b->n_chunks), dim3(256), 0, st, b->d_images, b->d_chunks,
-                                   cell_keys, rank, p.pfa, p.nms_mode);
-                break;
+        // every level's window (at most (2r+1)/s + 4 pixels wide) within 2 x 2 cells?
+        bool fix2 = true;
+        for (int l = 0; l < p.n_levels; l++) {
+            const double s_l = ctx->scale_q16[l] / 65536.0;
+            if ((2 * p.nms_radius + 1) / s_l + 3.0 > (double)ctx->cell[l]) fix2 = false;
         }
+#define VSFE_PFA_LAUNCH(R_)                                                                                       \
+    do {                                                                                                          \
+        if (fix2)                                                                                                 \
+            hipLaunchKernelGGL((pfa_eval_kernel<R_, true>), dim3(b->n_chunks), dim3(256), 0, st, b->d_images,    \
+                               b->d_chunks, cell_keys, rank, p.pfa, p.nms_mode);                                  \
+        else                                                                                                      \
+            hipLaunchKernelGGL((pfa_eval_kernel<R_, false>), dim3(b->n_chunks), dim3(256), 0, st, b->d_images,   \
+                               b->d_chunks, cell_keys, rank, p.pfa, p.nms_mode);                                  \
+    } while (0)
+        switch (p.nms_radius) {
+            case 0: VSFE_PFA_LAUNCH(0); break;
+            case 1: VSFE_PFA_LAUNCH(1); break;
+            case 2: VSFE_PFA_LAUNCH(2); break;
+            default: VSFE_PFA_LAUNCH(3); break;
+        }
+#undef VSFE_PFA_LAUNCH
         rc = check_launch("pyca_cull_aggregate (aggregation)");
         if (rc) return rc;
     }
