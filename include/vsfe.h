@@ -182,7 +182,7 @@ typedef struct {
 
 /* Per-level detector tile extents of a batch (host arrays of n_levels
  * entries).  A tile of tw x th pixels at level l packs
- * min(32, max(1, tw / cell_l)) x min(8, max(1, th / cell_l)) cells.
+ * min(32, max(1, tw / cell_l)) x min(4, max(1, th / cell_l)) cells.
  * Results never depend on the tiles.  set: EINVAL unless every level has
  * 8 <= tw <= 128 and 8 <= th <= 32; synchronises the device and replaces
  * the batch's detector work table, so HIP graphs captured earlier with this

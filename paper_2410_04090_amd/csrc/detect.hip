@@ -39,13 +39,12 @@ namespace vsfe {
 
 constexpr int FT_HALF = 64;                      // lanes per row; lane owns cols l and l + 64
 constexpr int FT_CHUNKS = 6;                     // 16-byte source chunks per row and half
-// LDS words per row: 70 used + 16-byte alignment slack; 100 = 36 mod 64, so
-// the rows of a 7 x 7 window (and rows 4 apart) fall in different banks
-constexpr int FT_W = 100;
+// LDS words per row: the 6 staged 16-byte chunks of each half (96 words)
+constexpr int FT_W = 96;
 constexpr int FT_MAX_ROWS = 32;
 constexpr int FT_ROWS = FT_MAX_ROWS + 6;
-constexpr int FT_MAX_CELLS = 256;               // at most 32 x 8 cells per tile
-constexpr int FT_QW = (FT_MAX_ROWS / 4) * 2 * FT_HALF;   // one wave's candidates (all of its pixels)
+constexpr int FT_MAX_CELLS = 128;               // at most 32 x 4 cells per tile
+constexpr int FT_QW = 512;                                // one wave's candidate queue (more: in rounds)
 
 struct DetParams {
     int eps_hi, eps_lo, p_min, p_max, border, eps_min, aligned;
@@ -190,7 +189,7 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 __device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 template <int PF, bool LO, bool P9>
-__global__ __launch_bounds__(256, 6) void fast_br_kernel(const ImageDev *__restrict__ imgs,
+__global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restrict__ imgs,
                                                       const DetItem *__restrict__ items,
                                                       const uint8_t *__restrict__ images,
                                                       const uint8_t *__restrict__ pyr,
@@ -346,13 +345,6 @@ __global__ __launch_bounds__(256, 6) void fast_br_kernel(const ImageDev *__restr
     const int incl = wave_incl_scan(cnt);
     const int qn = __builtin_amdgcn_readlane(incl, 63);
     uint16_t *const q = s_q[wv];
-    int pos = incl - cnt;
-    while (cm) {
-        const int bit = __builtin_ctz(cm);
-        cm &= cm - 1;
-        q[pos++] = (uint16_t)(((wv + 4 * (bit & 15)) << 7) | (lane + FT_HALF * (bit >> 4)));
-    }
-    wave_lds_fence();
 
     const uint16_t *t16 = (const uint16_t *)tile;
     // the 16 ring pixels and the centre of tile pixel (r, col), from LDS
@@ -404,6 +396,22 @@ __global__ __launch_bounds__(256, 6) void fast_br_kernel(const ImageDev *__restr
         }
     };
 
+    // The queue holds FT_QW entries; a wave with more candidates (dense
+    // texture) takes them in rounds, each screened and decided in full.
+    for (int r0 = 0; r0 < qn; r0 += FT_QW) {
+    {
+        uint32_t mm = cm;
+        int pos = incl - cnt;
+        while (mm) {
+            const int bit = __builtin_ctz(mm);
+            mm &= mm - 1;
+            if (pos >= r0 && pos < r0 + FT_QW)
+                q[pos - r0] = (uint16_t)(((wv + 4 * (bit & 15)) << 7) | (lane + FT_HALF * (bit >> 4)));
+            pos++;
+        }
+    }
+    wave_lds_fence();
+    const int qr = min(FT_QW, qn - r0);
     // 3b. screen every candidate densely: a run >= p_min at the weaker
     //     threshold is necessary for a corner at either threshold.  Survivors
     //     (entry = cmin << 14 | rd << 13 | rb << 12 | row << 7 | column) go to
@@ -413,9 +421,9 @@ __global__ __launch_bounds__(256, 6) void fast_br_kernel(const ImageDev *__restr
     // survivor never overwrites an entry that is still to be read
     uint16_t *const q2 = q;
     int n2 = 0;                                  // survivors so far (uniform)
-    for (int base = 0; base < qn; base += 64) {
+    for (int base = 0; base < qr; base += 64) {
         const int i = base + lane;
-        const bool act = i < qn;
+        const bool act = i < qr;
         const int e = act ? q[i] : 0;
         const int r = (e >> 7) & 63, col = e & 127;
         int p[16];
@@ -463,6 +471,8 @@ __global__ __launch_bounds__(256, 6) void fast_br_kernel(const ImageDev *__restr
         const int e = q2[i];
         finish((e >> 7) & 31, e & 127, (e >> 12) & 1, (e >> 13) & 1, (e >> 14) & 1);
     }
+    wave_lds_fence();
+    }  // rounds
     __syncthreads();
     for (int k = tid; k < nk; k += 256) {
         const uint32_t hi = s_hi[k], lo = s_lo[k];

@@ -18,7 +18,7 @@ namespace vsfe {
 
 static void cells_per_tile(int tile_w, int tile_h, int cell, int *nkx, int *nky) {
     *nkx = std::min(32, std::max(1, tile_w / cell));
-    *nky = std::min(8, std::max(1, tile_h / cell));     // at most 32 x 8 cells (detector LDS)
+    *nky = std::min(4, std::max(1, tile_h / cell));     // at most 32 x 4 cells (detector LDS)
 }
 
 void det_items_level(const vsfe_batch *b, int level, int tile_w, int tile_h, std::vector<DetItem> *out) {
