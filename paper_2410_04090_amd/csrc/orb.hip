@@ -23,6 +23,8 @@
 // The whole-level smoothed pyramid never touches HBM.
 #include <string.h>
 
+#include <algorithm>
+
 #include "vsfe_internal.h"
 
 namespace vsfe {
@@ -79,170 +81,211 @@ __device__ __forceinline__ uint32_t fetch4c(const uint8_t *row, int x, int w, bo
     return v;
 }
 
+// Persistent waves: wave w takes keypoint slots w, w + W, w + 2W, ... and
+// loads the next keypoint's neighbourhood into registers while it computes
+// the current one.  The per-lane constant tables are read once, and the
+// current keypoint's pattern is read before the next prefetch is issued, so
+// no wait inside the loop waits for the prefetch.
 __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ imgs, const uint8_t *__restrict__ images,
                                                   const uint8_t *__restrict__ pyr, vsfe_kp_soa kps,
                                                   const int32_t *__restrict__ kp_count,
                                                   const int8_t *__restrict__ pat_rot, uint32_t *__restrict__ desc,
-                                                  OrbArgs a) {
+                                                  OrbArgs a, int64_t n_slots) {
     __shared__ __attribute__((aligned(16))) uint32_t s_r[ORB_WAVES][R_BYTES / 4];
     __shared__ __attribute__((aligned(16))) uint32_t s_ht[ORB_WAVES][HT_BYTES / 4];
     __shared__ __attribute__((aligned(16))) uint32_t s_b[ORB_WAVES][B_BYTES / 4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t slot = (int64_t)xcd_item(blockIdx.x, gridDim.x) * ORB_WAVES + wave;
-    const int image = (int)(slot / a.n_max);
-    const int i = (int)(slot - (int64_t)image * a.n_max);
-    const bool active = image < a.n_images && i < kp_count[image];
+    const int mrow = lane & 15, grp = lane >> 4;
     uint8_t *R = (uint8_t *)s_r[wave];
     uint8_t *HT = (uint8_t *)s_ht[wave];
     uint8_t *BT = (uint8_t *)s_b[wave];
 
-    int delta = 0;
-    if (active) {
-        const int x = kps.x[slot], y = kps.y[slot], lvl = kps.level[slot];
+    // per-lane constants
+    uint32_t d_ones[8], d_ramp[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        d_ones[k] = lane < 31 ? c_disc.ones[lane][k] : 0u;
+        d_ramp[k] = lane < 31 ? c_disc.ramp[lane][k] : 0u;
+    }
+    uint64_t bh[2][2], va[2][2];
+#pragma unroll
+    for (int kc = 0; kc < 2; kc++)
+#pragma unroll
+        for (int t2 = 0; t2 < 2; t2++) {
+            bh[kc][t2] = c_smooth.hb[kc][t2][lane];
+            va[kc][t2] = c_smooth.va[kc][t2][lane];
+        }
+    int64_t bx = 0, by = 0;
+    if (lane < 30) {
+        bx = a.tab.bin_x[lane];
+        by = a.tab.bin_y[lane];
+    }
+
+    const int64_t nw = (int64_t)gridDim.x * ORB_WAVES;
+    const int64_t first = (int64_t)xcd_item(blockIdx.x, gridDim.x) * ORB_WAVES + wave;
+
+    // prefetched state of the next keypoint
+    bool p_act = false;
+    int p_delta = 0;
+    uint32_t p_v[6];
+    auto fetch = [&](int64_t s) {
+        const int image = (int)(s / a.n_max);
+        const int i = (int)(s - (int64_t)image * a.n_max);
+        p_act = image < a.n_images && i < kp_count[image];
+        if (!p_act) return;
+        const int x = kps.x[s], y = kps.y[s], lvl = kps.level[s];
         const LevelDev lv = imgs[image].lv[lvl];
         const uint8_t *src = (lvl == 0 ? images : pyr) + lv.offset;
         const bool aligned = lvl > 0 || a.aligned0;
         const int xs = (x - 18) & ~3;
-        delta = (x - 18) - xs;
-        uint32_t v[6];
+        p_delta = (x - 18) - xs;
 #pragma unroll
         for (int u = 0; u < 6; u++) {
             const int t = lane + 64 * u;
+            p_v[u] = 0u;
             if (t < 37 * 10) {
                 const int r = t / 10, m = t - r * 10;
                 const int gy = min(max(y - 18 + r, 0), lv.h - 1);
-                v[u] = fetch4c(src + (int64_t)gy * lv.pitch, xs + 4 * m, lv.w, aligned);
+                p_v[u] = fetch4c(src + (int64_t)gy * lv.pitch, xs + 4 * m, lv.w, aligned);
             }
         }
+    };
+    if (first < n_slots) fetch(first);
+
+    for (int64_t slot = first; slot < n_slots; slot += nw) {
+        const bool active = p_act;
+        const int delta = p_delta;
+        if (active) {
 #pragma unroll
-        for (int u = 0; u < 6; u++) {
-            const int t = lane + 64 * u;
-            if (t < 37 * 10) s_r[wave][(t / 10) * (R_STRIDE / 4) + t % 10] = v[u];
-        }
-    }
-    wave_lds_fence();
-    // intensity centroid: lane v' = v + 15 < 31 sums its disc row
-    int m10 = 0, m01 = 0;
-    if (active && lane < 31) {
-        const int al = (delta + 3) & 3;
-        const uint32_t *w = (const uint32_t *)(R + (lane + 3) * R_STRIDE + ((delta + 3) & ~3));
-        uint32_t S = 0, T = 0;
-        uint32_t prev = w[0];
-#pragma unroll
-        for (int k = 0; k < 8; k++) {
-            const uint32_t nxt = w[k + 1];
-            const uint32_t b4 = __builtin_amdgcn_alignbyte(nxt, prev, al);
-            S = __builtin_amdgcn_udot4(b4, c_disc.ones[lane][k], S, false);
-            T = __builtin_amdgcn_udot4(b4, c_disc.ramp[lane][k], T, false);
-            prev = nxt;
-        }
-        m10 = (int)T - 16 * (int)S;
-        m01 = (lane - 15) * (int)S;
-    }
-    const int mrow = lane & 15, grp = lane >> 4;
-    if (active && a.blur) {
-        // horizontal pass on MFMA: H[r][c] = sum_j R'[r][j] K0[j][c] with
-        // R'[r][j] = R[r][j + delta] - 128 (signed bytes), so the rounded
-        // output is (acc + 128 * 256 + 128) >> 8; 3 row tiles x 2 column
-        // tiles x 2 K chunks.  Written transposed, 4 rows per dword.
-        uint64_t bh[2][2];
-#pragma unroll
-        for (int kc = 0; kc < 2; kc++)
-#pragma unroll
-            for (int nt = 0; nt < 2; nt++) bh[kc][nt] = c_smooth.hb[kc][nt][lane];
-#pragma unroll
-        for (int mt = 0; mt < 3; mt++) {
-            i32x4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-#pragma unroll
-            for (int kc = 0; kc < 2; kc++) {
-                const uint32_t *w = (const uint32_t *)(R + (16 * mt + mrow) * R_STRIDE + 32 * kc + 8 * grp);
-                const uint32_t d0 = w[0], d1 = w[1], d2 = w[2];
-                const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, delta) ^ 0x80808080u;
-                const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, delta) ^ 0x80808080u;
-                const long av = (long)(((uint64_t)hi << 32) | lo);
-#pragma unroll
-                for (int nt = 0; nt < 2; nt++)
-                    acc[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8(av, (long)bh[kc][nt], acc[nt], 0, 0, 0);
-            }
-#pragma unroll
-            for (int nt = 0; nt < 2; nt++) {
-                uint32_t word = 0;
-#pragma unroll
-                for (int r = 0; r < 4; r++) word |= (uint32_t)((acc[nt][r] + 32896) >> 8) << (8 * r);
-                *(uint32_t *)(HT + (16 * nt + mrow) * HT_STRIDE + 16 * mt + 4 * grp) = word;
+            for (int u = 0; u < 6; u++) {
+                const int t = lane + 64 * u;
+                if (t < 37 * 10) s_r[wave][(t / 10) * (R_STRIDE / 4) + t % 10] = p_v[u];
             }
         }
-    }
+        wave_lds_fence();
+
+        // intensity centroid: lane v' = v + 15 < 31 sums its disc row
+        int m10 = 0, m01 = 0;
+        if (active && lane < 31) {
+            const int al = (delta + 3) & 3;
+            const uint32_t *w = (const uint32_t *)(R + (lane + 3) * R_STRIDE + ((delta + 3) & ~3));
+            uint32_t S = 0, T = 0;
+            uint32_t prev = w[0];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        m10 += __shfl_xor(m10, o);
-        m01 += __shfl_xor(m01, o);
-    }
-    wave_lds_fence();
-    if (active) {
-        if (a.blur) {
-            // vertical pass on MFMA: V[r'][c] = sum_r Kv[r'][r] (H[r][c] - 128),
-            // B read from the transposed H (8 rows of one column per lane);
-            // the output is written transposed, 4 rows per dword
+            for (int k = 0; k < 8; k++) {
+                const uint32_t nxt = w[k + 1];
+                const uint32_t b4 = __builtin_amdgcn_alignbyte(nxt, prev, al);
+                S = __builtin_amdgcn_udot4(b4, d_ones[k], S, false);
+                T = __builtin_amdgcn_udot4(b4, d_ramp[k], T, false);
+                prev = nxt;
+            }
+            m10 = (int)T - 16 * (int)S;
+            m01 = (lane - 15) * (int)S;
+        }
 #pragma unroll
-            for (int mt = 0; mt < 2; mt++) {
-                i32x4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+        for (int o = 32; o > 0; o >>= 1) {
+            m10 += __shfl_xor(m10, o);
+            m01 += __shfl_xor(m01, o);
+        }
+        // orientation bin: lane j < 30 tests angle(m) >= angle(boundary j)
+        bool ge = false;
+        if (lane < 30) {
+            const int hm = half_plane(m10, m01), hb = half_plane(bx, by);
+            ge = hm != hb ? hm > hb : (bx * (int64_t)m01 - by * (int64_t)m10 >= 0);
+        }
+        const uint64_t gem = __ballot(ge);
+        const int bin = (m10 == 0 && m01 == 0) ? 0 : (__popcll(gem) % 30);
+        // this keypoint's rotated pattern, then the next keypoint's rows
+        char4 qv[4];
+        if (active) {
+            const int8_t *pr = pat_rot + (int64_t)bin * 256 * 4;
 #pragma unroll
-                for (int kc = 0; kc < 2; kc++) {
-                    const long av = (long)c_smooth.va[kc][mt][lane];
+            for (int rnd = 0; rnd < 4; rnd++) qv[rnd] = *(const char4 *)(pr + 4 * (rnd * 64 + lane));
+        }
+        if (slot + nw < n_slots) fetch(slot + nw);
+        else p_act = false;
+
+        if (active) {
+            if (a.blur) {
+                // horizontal pass on MFMA: H[r][c] = sum_j R'[r][j] K0[j][c] with
+                // R'[r][j] = R[r][j + delta] - 128 (signed bytes), so the rounded
+                // output is (acc + 128 * 256 + 128) >> 8; 3 row tiles x 2 column
+                // tiles x 2 K chunks.  Written transposed, 4 rows per dword.
+#pragma unroll
+                for (int mt = 0; mt < 3; mt++) {
+                    i32x4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+                    for (int kc = 0; kc < 2; kc++) {
+                        const uint32_t *w = (const uint32_t *)(R + (16 * mt + mrow) * R_STRIDE + 32 * kc + 8 * grp);
+                        const uint32_t d0 = w[0], d1 = w[1], d2 = w[2];
+                        const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, delta) ^ 0x80808080u;
+                        const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, delta) ^ 0x80808080u;
+                        const long av = (long)(((uint64_t)hi << 32) | lo);
+#pragma unroll
+                        for (int nt = 0; nt < 2; nt++)
+                            acc[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8(av, (long)bh[kc][nt], acc[nt], 0, 0, 0);
+                    }
 #pragma unroll
                     for (int nt = 0; nt < 2; nt++) {
-                        const uint2 hv = *(const uint2 *)(HT + (16 * nt + mrow) * HT_STRIDE + 32 * kc + 8 * grp);
-                        const long bv = (long)((((uint64_t)(hv.y ^ 0x80808080u)) << 32) | (hv.x ^ 0x80808080u));
-                        acc[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8(av, bv, acc[nt], 0, 0, 0);
+                        uint32_t word = 0;
+#pragma unroll
+                        for (int r = 0; r < 4; r++) word |= (uint32_t)((acc[nt][r] + 32896) >> 8) << (8 * r);
+                        *(uint32_t *)(HT + (16 * nt + mrow) * HT_STRIDE + 16 * mt + 4 * grp) = word;
                     }
                 }
+                wave_lds_fence();
+                // vertical pass on MFMA: V[r'][c] = sum_r Kv[r'][r] (H[r][c] - 128),
+                // B read from the transposed H (8 rows of one column per lane);
+                // the output is written transposed, 4 rows per dword
 #pragma unroll
-                for (int nt = 0; nt < 2; nt++) {
-                    uint32_t word = 0;
+                for (int mt = 0; mt < 2; mt++) {
+                    i32x4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
-                    for (int r = 0; r < 4; r++) word |= (uint32_t)((acc[nt][r] + 32896) >> 8) << (8 * r);
-                    s_b[wave][((16 * nt + mrow) * B_STRIDE + 16 * mt + 4 * grp) >> 2] = word;
+                    for (int kc = 0; kc < 2; kc++) {
+#pragma unroll
+                        for (int nt = 0; nt < 2; nt++) {
+                            const uint2 hv = *(const uint2 *)(HT + (16 * nt + mrow) * HT_STRIDE + 32 * kc + 8 * grp);
+                            const long bv = (long)((((uint64_t)(hv.y ^ 0x80808080u)) << 32) | (hv.x ^ 0x80808080u));
+                            acc[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)va[kc][mt], bv, acc[nt], 0, 0, 0);
+                        }
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < 2; nt++) {
+                        uint32_t word = 0;
+#pragma unroll
+                        for (int r = 0; r < 4; r++) word |= (uint32_t)((acc[nt][r] + 32896) >> 8) << (8 * r);
+                        s_b[wave][((16 * nt + mrow) * B_STRIDE + 16 * mt + 4 * grp) >> 2] = word;
+                    }
+                }
+            } else {
+                for (int t = lane; t < 31 * 31; t += 64) {
+                    const int c = t / 31, r = t - c * 31;
+                    BT[c * B_STRIDE + r] = R[(r + 3) * R_STRIDE + delta + c + 3];
                 }
             }
-        } else {
-            for (int t = lane; t < 31 * 31; t += 64) {
-                const int c = t / 31, r = t - c * 31;
-                BT[c * B_STRIDE + r] = R[(r + 3) * R_STRIDE + delta + c + 3];
+        }
+        wave_lds_fence();
+        if (active) {
+            uint32_t words[8];
+#pragma unroll
+            for (int rnd = 0; rnd < 4; rnd++) {
+                const char4 q = qv[rnd];
+                const int pa = BT[(15 + q.x) * B_STRIDE + 15 + q.y];
+                const int pb = BT[(15 + q.z) * B_STRIDE + 15 + q.w];
+                const uint64_t bits = __ballot(pa < pb);
+                words[2 * rnd] = (uint32_t)bits;
+                words[2 * rnd + 1] = (uint32_t)(bits >> 32);
             }
-        }
-    }
-    // orientation bin: lane j < 30 tests angle(m) >= angle(boundary j)
-    bool ge = false;
-    if (lane < 30) {
-        const int64_t bx = a.tab.bin_x[lane], by = a.tab.bin_y[lane];
-        const int hm = half_plane(m10, m01), hb = half_plane(bx, by);
-        ge = hm != hb ? hm > hb : (bx * (int64_t)m01 - by * (int64_t)m10 >= 0);
-    }
-    const uint64_t gem = __ballot(ge);
-    const int bin = (m10 == 0 && m01 == 0) ? 0 : (__popcll(gem) % 30);
-    wave_lds_fence();
-    if (active) {
-        const int8_t *pr = pat_rot + (int64_t)bin * 256 * 4;
-        uint32_t words[8];
+            if (lane < 8) {
+                uint32_t w = words[0];
 #pragma unroll
-        for (int rnd = 0; rnd < 4; rnd++) {
-            const int t = rnd * 64 + lane;
-            const char4 q = *(const char4 *)(pr + 4 * t);
-            const int va = BT[(15 + q.x) * B_STRIDE + 15 + q.y];
-            const int vb = BT[(15 + q.z) * B_STRIDE + 15 + q.w];
-            const uint64_t bits = __ballot(va < vb);
-            words[2 * rnd] = (uint32_t)bits;
-            words[2 * rnd + 1] = (uint32_t)(bits >> 32);
+                for (int k = 1; k < 8; k++)
+                    if (lane == k) w = words[k];
+                desc[slot * 8 + lane] = w;
+            }
+            if (lane == 0) kps.bin[slot] = (uint8_t)bin;
         }
-        if (lane < 8) {
-            uint32_t w = words[0];
-#pragma unroll
-            for (int k = 1; k < 8; k++)
-                if (lane == k) w = words[k];
-            desc[slot * 8 + lane] = w;
-        }
-        if (lane == 0) kps.bin[slot] = (uint8_t)bin;
+        wave_lds_fence();
     }
 }
 
@@ -308,9 +351,19 @@ extern "C" int32_t orb_describe(const vsfe_ctx *ctx, const vsfe_batch *b, const 
     a.blur = ctx->p.blur;
     a.aligned0 = b->aligned_input && (((uintptr_t)images & 3) == 0) ? 1 : 0;
     const int64_t slots = b->info.kp_capacity;
-    const int64_t blocks = (slots + ORB_WAVES - 1) / ORB_WAVES;
+    int64_t blocks = (slots + ORB_WAVES - 1) / ORB_WAVES;
     if (blocks <= 0) return VSFE_OK;
+    static const int64_t resident = [] {
+        int dev = 0, n_cu = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, orb_kernel, 256, 0) != hipSuccess || n_cu < 1 ||
+            per_cu < 1)
+            return (int64_t)2048;
+        return (int64_t)n_cu * per_cu;
+    }();
+    blocks = std::min(blocks, resident);
     hipLaunchKernelGGL(orb_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, b->d_images, images, pyr,
-                       *kps, kp_count, ctx->d_pattern_rot, desc, a);
+                       *kps, kp_count, ctx->d_pattern_rot, desc, a, slots);
     return check_launch("orb_describe");
 }
