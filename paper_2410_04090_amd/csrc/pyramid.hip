@@ -7,18 +7,24 @@
 // exact sum, factored: h = 256 a + fx (b - a), v = 256 h0 + fy (h1 - h0)).
 //
 // One launch per level covers that level of every image.  A block writes a
-// 128 x 32 output tile: it stages the source window (chosen on the host, at
-// most 256 x 44 bytes) in LDS with 16-byte loads, reads per-column and per-
-// row source indices and weights from host-built tables (no division on the
-// device), and each thread produces a 4 x 4 block of outputs.  Output rows
-// of a block share source rows, so each needed source row is lerped
-// horizontally once per column; results are stored as 32-bit words.
+// 256 x 16 output tile: it stages the source window (chosen on the host, at
+// most 336 x 24 bytes) in LDS with 16-byte loads and reads per-column and
+// per-row source indices and weights from host-built tables (no division on
+// the device).  Each lane produces 4 columns of its wave's 4 rows, so the
+// source rows are uniform per wave: every needed source row is lerped
+// horizontally once, two columns per packed 16-bit multiply-add
+// (a (256 - fx) + b fx <= 65280 fits), with the 4 source bytes of a column
+// pair gathered by one v_perm from two LDS dwords; the vertical lerp is a
+// 32-bit multiply-add per output whose byte 2 is the rounded result, and the
+// 4 outputs are stored as one 32-bit word.
 #include "vsfe_internal.h"
 
 namespace vsfe {
 
 constexpr int PYR_LDS_W = PYR_SW + 16;  // padded row stride (bank spread), 16-byte aligned
 constexpr int PYR_TASKS = (PYR_SH * (PYR_SW / 16) + 255) / 256;
+
+typedef unsigned short pu2 __attribute__((ext_vector_type(2)));
 
 // 16 consecutive bytes of a row from x, coordinates clamped to [0, w).
 __device__ __forceinline__ uint4 fetch16c(const uint8_t *row, int x, int w, bool aligned) {
@@ -65,49 +71,65 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
         if (at[u] >= 0) ((uint4 *)s_src)[at[u]] = v[u];
     __syncthreads();
 
-    const uint8_t *sb = (const uint8_t *)s_src;
-    const int ox = it.tx * PYR_TW + (tid & 31) * 4;
-    const int oy0 = it.ty * PYR_TH + (tid >> 5) * 4;
-    if (ox >= d.w || oy0 >= d.h) return;
-    int xa[4], fx[4];
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int oy0 = it.ty * PYR_TH + 4 * wave;           // uniform
+    if (oy0 >= d.h) return;
+    const int ox = it.tx * PYR_TW + 4 * lane;
+    // columns: source index (window-local) and weight of the lane's 4 outputs
+    int o[4], fx[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const uint32_t e = coord[d.xtab + min(ox + j, d.w - 1)];
-        xa[j] = (int)(e & 0xFFFFu) - (int)it.xs;
+        o[j] = (int)(e & 0xFFFFu) - (int)it.xs;
         fx[j] = (int)(e >> 16);
     }
-    // horizontal lerp of source row `ya` (LDS-local) for the 4 columns
-    auto hrow = [&](int ya, int *h) {
+    // byte selectors of (a0, a1), (b0, b1), (a2, a3), (b2, b3) within the
+    // two dwords at base01 / base23 (0x0c selects a zero byte)
+    const int base01 = o[0] & ~3, base23 = o[2] & ~3;
+    const uint32_t selA01 = (uint32_t)(o[0] - base01) | 0x0C00u | ((uint32_t)(o[1] - base01) << 16) | 0x0C000000u;
+    const uint32_t selA23 = (uint32_t)(o[2] - base23) | 0x0C00u | ((uint32_t)(o[3] - base23) << 16) | 0x0C000000u;
+    const uint32_t selB01 = selA01 + 0x00010001u, selB23 = selA23 + 0x00010001u;
+    const pu2 W01 = {(unsigned short)(256 - fx[0]), (unsigned short)(256 - fx[1])};
+    const pu2 W23 = {(unsigned short)(256 - fx[2]), (unsigned short)(256 - fx[3])};
+    const pu2 F01 = {(unsigned short)fx[0], (unsigned short)fx[1]};
+    const pu2 F23 = {(unsigned short)fx[2], (unsigned short)fx[3]};
+    const uint8_t *sb = (const uint8_t *)s_src;
+    // horizontal lerps (x 256) of window row ya for the 4 columns, as two u16 pairs
+    auto hrow = [&](int ya, pu2 &h01, pu2 &h23) {
         const uint8_t *r = sb + ya * PYR_LDS_W;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int a = r[xa[j]], b = r[xa[j] + 1];
-            h[j] = (a << 8) + fx[j] * (b - a);
-        }
+        const uint32_t d0 = *(const uint32_t *)(r + base01), d1 = *(const uint32_t *)(r + base01 + 4);
+        const uint32_t e0 = *(const uint32_t *)(r + base23), e1 = *(const uint32_t *)(r + base23 + 4);
+        const pu2 A01 = __builtin_bit_cast(pu2, __builtin_amdgcn_perm(d1, d0, selA01));
+        const pu2 B01 = __builtin_bit_cast(pu2, __builtin_amdgcn_perm(d1, d0, selB01));
+        const pu2 A23 = __builtin_bit_cast(pu2, __builtin_amdgcn_perm(e1, e0, selA23));
+        const pu2 B23 = __builtin_bit_cast(pu2, __builtin_amdgcn_perm(e1, e0, selB23));
+        h01 = A01 * W01 + B01 * F01;
+        h23 = A23 * W23 + B23 * F23;
     };
-    int cur_row = -1;
-    int h0[4], h1[4];
+    int cur = -2;
+    pu2 t01, t23, u01, u23;                              // rows cur, cur + 1
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const int oy = oy0 + k;
-        if (oy >= d.h) break;
+        if (oy >= d.h) break;                            // uniform
         const uint32_t e = coord[d.ytab + oy];
-        const int ya = (int)(e & 0xFFFFu) - (int)it.ys, fy = (int)(e >> 16);
-        if (ya == cur_row + 1 && cur_row >= 0) {
-#pragma unroll
-            for (int j = 0; j < 4; j++) h0[j] = h1[j];
-            hrow(ya + 1, h1);
-        } else if (ya != cur_row) {
-            hrow(ya, h0);
-            hrow(ya + 1, h1);
+        const int ya = (int)(e & 0xFFFFu) - (int)it.ys;
+        const uint32_t fy = e >> 16, wy = 256u - fy;
+        if (ya == cur + 1) {                             // slide by one row
+            t01 = u01;
+            t23 = u23;
+            hrow(ya + 1, u01, u23);
+        } else if (ya != cur) {
+            hrow(ya, t01, t23);
+            hrow(ya + 1, u01, u23);
         }
-        cur_row = ya;
-        uint32_t word = 0;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int v = ((h0[j] << 8) + fy * (h1[j] - h0[j]) + 32768) >> 16;
-            word |= (uint32_t)v << (8 * j);
-        }
+        cur = ya;
+        // (h0 (256 - fy) + h1 fy + 2^15) >> 16 is byte 2 of the sum
+        const uint32_t s0 = (uint32_t)t01.x * wy + (uint32_t)u01.x * fy + 32768u;
+        const uint32_t s1 = (uint32_t)t01.y * wy + (uint32_t)u01.y * fy + 32768u;
+        const uint32_t s2 = (uint32_t)t23.x * wy + (uint32_t)u23.x * fy + 32768u;
+        const uint32_t s3 = (uint32_t)t23.y * wy + (uint32_t)u23.y * fy + 32768u;
+        const uint32_t word = __builtin_amdgcn_perm(s1, s0, 0x0C0C0602u) | (__builtin_amdgcn_perm(s3, s2, 0x0C0C0602u) << 16);
         uint8_t *out = dst + (int64_t)oy * d.pitch + ox;
         if (ox + 3 < d.w) {
             *(uint32_t *)out = word;
