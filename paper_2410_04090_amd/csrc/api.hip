@@ -335,7 +335,7 @@ int32_t vsfe_ctx_create(const vsfe_params *p, const int8_t *pattern, vsfe_ctx **
         c->tables.bin_x[k] = (int32_t)lround(16384.0 * cos(bnd));
         c->tables.bin_y[k] = (int32_t)lround(16384.0 * sin(bnd));
     }
-    std::vector<int8_t> rot(30 * 256 * 4);
+    std::vector<uint32_t> rot(30 * 256);
     for (int k = 0; k < 30; k++)
         for (int t = 0; t < 256; t++)
             for (int e = 0; e < 2; e++) {
@@ -346,15 +346,14 @@ int32_t vsfe_ctx_create(const vsfe_params *p, const int8_t *pattern, vsfe_ctx **
                     delete c;
                     return fail(VSFE_EINVAL, "rotated pattern leaves the 31x31 patch");
                 }
-                rot[(k * 256 + t) * 4 + 2 * e] = (int8_t)ur;
-                rot[(k * 256 + t) * 4 + 2 * e + 1] = (int8_t)vr;
+                rot[k * 256 + t] |= (uint32_t)((15 + ur) * ORB_PATCH_STRIDE + 15 + vr) << (16 * e);
             }
-    if (hipMalloc((void **)&c->d_pattern_rot, rot.size()) != hipSuccess) {
+    if (hipMalloc((void **)&c->d_pattern_off, rot.size() * sizeof(uint32_t)) != hipSuccess) {
         delete c;
         return fail(VSFE_EHIP, "hipMalloc of the pattern table failed");
     }
-    if (hipMemcpy(c->d_pattern_rot, rot.data(), rot.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(c->d_pattern_rot);
+    if (hipMemcpy(c->d_pattern_off, rot.data(), rot.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(c->d_pattern_off);
         delete c;
         return fail(VSFE_EHIP, "upload of the pattern table failed");
     }
@@ -364,7 +363,7 @@ int32_t vsfe_ctx_create(const vsfe_params *p, const int8_t *pattern, vsfe_ctx **
 
 int32_t vsfe_ctx_destroy(vsfe_ctx *ctx) {
     if (!ctx) return VSFE_OK;
-    if (ctx->d_pattern_rot) (void)hipFree(ctx->d_pattern_rot);
+    if (ctx->d_pattern_off) (void)hipFree(ctx->d_pattern_off);
     delete ctx;
     return VSFE_OK;
 }

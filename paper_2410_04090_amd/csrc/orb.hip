@@ -3,23 +3,30 @@
 //
 // One 64-lane wave per keypoint.  The wave stages the 37 x 37 neighbourhood
 // of its keypoint in LDS with 32-bit loads (coordinates clamped to the
-// level, which makes the clamp-to-edge smoothing exact), then:
+// level, which makes the clamp-to-edge smoothing exact), each byte stored
+// as p - 128 (a signed byte), then:
 //  * intensity centroid over the disc u^2 + v^2 <= 225 of the unsmoothed
 //    level, one lane per disc row: S_v = sum_u I and T_v = sum_u (u+16) I as
-//    dot products of 4 bytes against constant weight words (v_dot4_u32_u8);
-//    m10 = sum_v (T_v - 16 S_v), m01 = sum_v v S_v, reduced across the wave;
+//    signed dot products of 4 bytes against constant weight words
+//    (v_dot4_i32_i8) plus the per-row constants that undo the -128;
+//    m10 = sum_v (T_v - 16 S_v), m01 = sum_v v S_v, reduced on the DPP network;
 //  * orientation bin: 30 lanes compare m with the Q14 bin boundaries at
 //    6 + 12 j degrees by exact integer half-plane / cross-product tests,
 //    a ballot counts them (bin = count mod 30, 0 for m = 0);
 //  * smoothing only of the 31 x 31 patch the tests can touch, separable
 //    7-tap [18 33 49 56 49 33 18] / 256 with each pass rounded half up;
 //    both passes are exact integer products with a banded weight matrix on
-//    v_mfma_i32_16x16x32_i8 (pixels offset by -128 to fit signed bytes, the
-//    offset added back as 128 * 256 before rounding); the horizontal pass
-//    writes its result transposed so the vertical pass reads 8 rows of one
-//    column per lane, and the final patch is stored transposed;
-//  * 256 tests on the bin-rotated pattern (precomputed per bin in the
-//    context), 64 per ballot, written as 8 words.
+//    v_mfma_i32_16x16x32_i8 over the signed bytes.  The accumulators start
+//    at the rounding constant, so byte 1 of each one is the rounded result:
+//    the horizontal pass starts at 128 and yields H - 128 directly as the
+//    signed input of the vertical pass, which starts at 128 * 256 + 128 and
+//    yields the unsigned result; four results pack into a word with two
+//    v_perm.  The horizontal pass writes its result transposed so the
+//    vertical pass reads 8 rows of one column per lane, and the final patch
+//    is stored transposed;
+//  * 256 tests on the bin-rotated pattern (per bin, precomputed in the
+//    context as byte offsets into the stored patch), 64 per ballot, written
+//    as 8 words.
 // The whole-level smoothed pyramid never touches HBM.
 #include <string.h>
 
@@ -34,7 +41,7 @@ constexpr int R_STRIDE = 40;      // staged 37 x 37 neighbourhood, one row per 4
 constexpr int R_BYTES = 48 * R_STRIDE + 32;   // 48 rows (3 MFMA row tiles) + read slack
 constexpr int HT_STRIDE = 48;     // horizontal pass, transposed: [column][row], 37 of 48 rows used
 constexpr int HT_BYTES = 32 * HT_STRIDE + 16;
-constexpr int B_STRIDE = 32;      // final smoothed patch, transposed: [column][row], 31 used
+constexpr int B_STRIDE = ORB_PATCH_STRIDE;   // final smoothed patch, transposed: [column][row], 31 used
 constexpr int B_BYTES = 32 * B_STRIDE;
 constexpr uint32_t W_LO = 18u | (33u << 8) | (49u << 16) | (56u << 24);
 constexpr uint32_t W_HI = 49u | (33u << 8) | (18u << 16);
@@ -42,6 +49,7 @@ constexpr uint32_t W_HI = 49u | (33u << 8) | (18u << 16);
 struct OrbArgs {
     OrbTables tab;
     int n_max, n_images, blur, aligned0;
+    int step_img, step_i;      // one wave's slot stride, as whole images plus slots
 };
 
 // Per disc row v = -15..15: byte u' (u = u' - 15) of 8 words; ones: 1 inside
@@ -73,39 +81,60 @@ __device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmc
 
 __device__ __forceinline__ int half_plane(int64_t x, int64_t y) { return (y < 0 || (y == 0 && x < 0)) ? 1 : 0; }
 
-__device__ __forceinline__ uint32_t fetch4c(const uint8_t *row, int x, int w, bool aligned) {
-    if (aligned && x >= 0 && x + 3 < w) return *(const uint32_t *)(row + x);
+__device__ __forceinline__ uint32_t fetch4c(const uint8_t *row, int x, int w) {
     uint32_t v = 0;
 #pragma unroll
     for (int j = 0; j < 4; j++) v |= (uint32_t)row[min(max(x + j, 0), w - 1)] << (8 * j);
     return v;
 }
 
-// Persistent waves: wave w takes keypoint slots w, w + W, w + 2W, ... and
-// loads the next keypoint's neighbourhood into registers while it computes
-// the current one.  The per-lane constant tables are read once, and the
-// current keypoint's pattern is read before the next prefetch is issued, so
-// no wait inside the loop waits for the prefetch.
+// Sum over lanes 0..31 on the DPP network (row shifts, then row 0's last
+// lane broadcast into row 1); valid in lane 31.
+__device__ __forceinline__ int sum_lanes32(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    return __builtin_amdgcn_readlane(v, 31);
+}
+
+// Byte 1 of four accumulators, packed into one word.
+__device__ __forceinline__ uint32_t pack_byte1(const i32x4 &a) {
+    return __builtin_amdgcn_perm((uint32_t)a[1], (uint32_t)a[0], 0x0C0C0501u) |
+           __builtin_amdgcn_perm((uint32_t)a[3], (uint32_t)a[2], 0x05010C0Cu);
+}
+
+// Persistent waves: a wave takes keypoint slots first, first + W, ... (W =
+// waves in the grid, walked as whole images plus slots so that no division
+// runs in the loop) and loads the next keypoint's neighbourhood into
+// registers while it computes the current one.  The per-lane constant
+// tables are read once, and the current keypoint's pattern is read before
+// the next prefetch is issued, so no wait inside the loop waits for the
+// prefetch.  Slot state is wave-uniform (scalar registers).
 __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ imgs, const uint8_t *__restrict__ images,
                                                   const uint8_t *__restrict__ pyr, vsfe_kp_soa kps,
                                                   const int32_t *__restrict__ kp_count,
-                                                  const int8_t *__restrict__ pat_rot, uint32_t *__restrict__ desc,
-                                                  OrbArgs a, int64_t n_slots) {
+                                                  const uint32_t *__restrict__ pat_off, uint32_t *__restrict__ desc,
+                                                  OrbArgs a) {
     __shared__ __attribute__((aligned(16))) uint32_t s_r[ORB_WAVES][R_BYTES / 4];
     __shared__ __attribute__((aligned(16))) uint32_t s_ht[ORB_WAVES][HT_BYTES / 4];
     __shared__ __attribute__((aligned(16))) uint32_t s_b[ORB_WAVES][B_BYTES / 4];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int mrow = lane & 15, grp = lane >> 4;
     uint8_t *R = (uint8_t *)s_r[wave];
     uint8_t *HT = (uint8_t *)s_ht[wave];
     uint8_t *BT = (uint8_t *)s_b[wave];
 
-    // per-lane constants
+    // per-lane constants; cS / cT undo the -128 of the staged bytes
     uint32_t d_ones[8], d_ramp[8];
+    int cS = 0, cT = 0;
 #pragma unroll
     for (int k = 0; k < 8; k++) {
         d_ones[k] = lane < 31 ? c_disc.ones[lane][k] : 0u;
         d_ramp[k] = lane < 31 ? c_disc.ramp[lane][k] : 0u;
+        cS += (int)__builtin_amdgcn_udot4(d_ones[k], 0x80808080u, 0u, false);
+        cT += (int)__builtin_amdgcn_udot4(d_ramp[k], 0x80808080u, 0u, false);
     }
     uint64_t bh[2][2], va[2][2];
 #pragma unroll
@@ -120,47 +149,60 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         bx = a.tab.bin_x[lane];
         by = a.tab.bin_y[lane];
     }
-
-    const int64_t nw = (int64_t)gridDim.x * ORB_WAVES;
-    const int64_t first = (int64_t)xcd_item(blockIdx.x, gridDim.x) * ORB_WAVES + wave;
+    // staging tasks of this lane: dword t = lane + 64 u is row t / 10, word t % 10
+    int t_row[6], t_word[6];
+#pragma unroll
+    for (int u = 0; u < 6; u++) {
+        const int t = lane + 64 * u;
+        t_row[u] = t / 10;
+        t_word[u] = t - 10 * t_row[u];
+    }
 
     // prefetched state of the next keypoint
     bool p_act = false;
     int p_delta = 0;
     uint32_t p_v[6];
-    auto fetch = [&](int64_t s) {
-        const int image = (int)(s / a.n_max);
-        const int i = (int)(s - (int64_t)image * a.n_max);
+    auto fetch = [&](int image, int i) {
         p_act = image < a.n_images && i < kp_count[image];
         if (!p_act) return;
-        const int x = kps.x[s], y = kps.y[s], lvl = kps.level[s];
+        const int64_t s = (int64_t)image * a.n_max + i;
+        const int x = __builtin_amdgcn_readfirstlane((int)kps.x[s]);
+        const int y = __builtin_amdgcn_readfirstlane((int)kps.y[s]);
+        const int lvl = __builtin_amdgcn_readfirstlane((int)kps.level[s]);
         const LevelDev lv = imgs[image].lv[lvl];
         const uint8_t *src = (lvl == 0 ? images : pyr) + lv.offset;
         const bool aligned = lvl > 0 || a.aligned0;
         const int xs = (x - 18) & ~3;
         p_delta = (x - 18) - xs;
+        if (aligned && y >= 18 && y + 18 < lv.h && xs >= 0 && xs + 40 <= lv.w) {
+            // the whole 40 x 37 window lies inside the level: plain 32-bit loads
+            const uint8_t *base = src + (int64_t)(y - 18) * lv.pitch + xs;
 #pragma unroll
-        for (int u = 0; u < 6; u++) {
-            const int t = lane + 64 * u;
-            p_v[u] = 0u;
-            if (t < 37 * 10) {
-                const int r = t / 10, m = t - r * 10;
-                const int gy = min(max(y - 18 + r, 0), lv.h - 1);
-                p_v[u] = fetch4c(src + (int64_t)gy * lv.pitch, xs + 4 * m, lv.w, aligned);
+            for (int u = 0; u < 6; u++)
+                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const uint32_t *)(base + t_row[u] * lv.pitch + 4 * t_word[u]) : 0u;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 6; u++) {
+                p_v[u] = 0u;
+                if (lane + 64 * u < 37 * 10) {
+                    const int gy = min(max(y - 18 + t_row[u], 0), lv.h - 1);
+                    p_v[u] = fetch4c(src + (int64_t)gy * lv.pitch, xs + 4 * t_word[u], lv.w);
+                }
             }
         }
     };
-    if (first < n_slots) fetch(first);
 
-    for (int64_t slot = first; slot < n_slots; slot += nw) {
+    const int first = xcd_item(blockIdx.x, gridDim.x) * ORB_WAVES + wave;
+    int cimg = first / a.n_max, ci = first - cimg * a.n_max;
+    if (cimg < a.n_images) fetch(cimg, ci);
+
+    while (cimg < a.n_images) {
         const bool active = p_act;
         const int delta = p_delta;
         if (active) {
 #pragma unroll
-            for (int u = 0; u < 6; u++) {
-                const int t = lane + 64 * u;
-                if (t < 37 * 10) s_r[wave][(t / 10) * (R_STRIDE / 4) + t % 10] = p_v[u];
-            }
+            for (int u = 0; u < 6; u++)
+                if (lane + 64 * u < 37 * 10) s_r[wave][t_row[u] * (R_STRIDE / 4) + t_word[u]] = p_v[u] ^ 0x80808080u;
         }
         wave_lds_fence();
 
@@ -169,24 +211,21 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         if (active && lane < 31) {
             const int al = (delta + 3) & 3;
             const uint32_t *w = (const uint32_t *)(R + (lane + 3) * R_STRIDE + ((delta + 3) & ~3));
-            uint32_t S = 0, T = 0;
+            int S = cS, T = cT;
             uint32_t prev = w[0];
 #pragma unroll
             for (int k = 0; k < 8; k++) {
                 const uint32_t nxt = w[k + 1];
                 const uint32_t b4 = __builtin_amdgcn_alignbyte(nxt, prev, al);
-                S = __builtin_amdgcn_udot4(b4, d_ones[k], S, false);
-                T = __builtin_amdgcn_udot4(b4, d_ramp[k], T, false);
+                S = __builtin_amdgcn_sdot4((int)b4, (int)d_ones[k], S, false);
+                T = __builtin_amdgcn_sdot4((int)b4, (int)d_ramp[k], T, false);
                 prev = nxt;
             }
-            m10 = (int)T - 16 * (int)S;
-            m01 = (lane - 15) * (int)S;
+            m10 = T - 16 * S;
+            m01 = (lane - 15) * S;
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            m10 += __shfl_xor(m10, o);
-            m01 += __shfl_xor(m01, o);
-        }
+        m10 = sum_lanes32(m10);
+        m01 = sum_lanes32(m01);
         // orientation bin: lane j < 30 tests angle(m) >= angle(boundary j)
         bool ge = false;
         if (lane < 30) {
@@ -196,71 +235,69 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         const uint64_t gem = __ballot(ge);
         const int bin = (m10 == 0 && m01 == 0) ? 0 : (__popcll(gem) % 30);
         // this keypoint's rotated pattern, then the next keypoint's rows
-        char4 qv[4];
+        uint32_t qv[4];
         if (active) {
-            const int8_t *pr = pat_rot + (int64_t)bin * 256 * 4;
+            const uint32_t *pr = pat_off + bin * 256;
 #pragma unroll
-            for (int rnd = 0; rnd < 4; rnd++) qv[rnd] = *(const char4 *)(pr + 4 * (rnd * 64 + lane));
+            for (int rnd = 0; rnd < 4; rnd++) qv[rnd] = pr[rnd * 64 + lane];
         }
-        if (slot + nw < n_slots) fetch(slot + nw);
+        const int64_t slot = (int64_t)cimg * a.n_max + ci;
+        cimg += a.step_img;
+        ci += a.step_i;
+        if (ci >= a.n_max) {
+            ci -= a.n_max;
+            cimg++;
+        }
+        if (cimg < a.n_images) fetch(cimg, ci);
         else p_act = false;
 
         if (active) {
             if (a.blur) {
-                // horizontal pass on MFMA: H[r][c] = sum_j R'[r][j] K0[j][c] with
-                // R'[r][j] = R[r][j + delta] - 128 (signed bytes), so the rounded
-                // output is (acc + 128 * 256 + 128) >> 8; 3 row tiles x 2 column
+                // horizontal pass on MFMA: H[r][c] - 128 = (128 + sum_j R'[r][j] K0[j][c]) >> 8
+                // with R'[r][j] = R[r][j + delta] - 128; 3 row tiles x 2 column
                 // tiles x 2 K chunks.  Written transposed, 4 rows per dword.
 #pragma unroll
                 for (int mt = 0; mt < 3; mt++) {
-                    i32x4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+                    i32x4 acc[2] = {{128, 128, 128, 128}, {128, 128, 128, 128}};
 #pragma unroll
                     for (int kc = 0; kc < 2; kc++) {
                         const uint32_t *w = (const uint32_t *)(R + (16 * mt + mrow) * R_STRIDE + 32 * kc + 8 * grp);
                         const uint32_t d0 = w[0], d1 = w[1], d2 = w[2];
-                        const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, delta) ^ 0x80808080u;
-                        const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, delta) ^ 0x80808080u;
+                        const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, delta);
+                        const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, delta);
                         const long av = (long)(((uint64_t)hi << 32) | lo);
 #pragma unroll
                         for (int nt = 0; nt < 2; nt++)
                             acc[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8(av, (long)bh[kc][nt], acc[nt], 0, 0, 0);
                     }
 #pragma unroll
-                    for (int nt = 0; nt < 2; nt++) {
-                        uint32_t word = 0;
-#pragma unroll
-                        for (int r = 0; r < 4; r++) word |= (uint32_t)((acc[nt][r] + 32896) >> 8) << (8 * r);
-                        *(uint32_t *)(HT + (16 * nt + mrow) * HT_STRIDE + 16 * mt + 4 * grp) = word;
-                    }
+                    for (int nt = 0; nt < 2; nt++)
+                        *(uint32_t *)(HT + (16 * nt + mrow) * HT_STRIDE + 16 * mt + 4 * grp) = pack_byte1(acc[nt]);
                 }
                 wave_lds_fence();
-                // vertical pass on MFMA: V[r'][c] = sum_r Kv[r'][r] (H[r][c] - 128),
+                // vertical pass on MFMA: V[r'][c] = (32896 + sum_r Kv[r'][r] (H[r][c] - 128)) >> 8,
                 // B read from the transposed H (8 rows of one column per lane);
                 // the output is written transposed, 4 rows per dword
 #pragma unroll
                 for (int mt = 0; mt < 2; mt++) {
-                    i32x4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+                    i32x4 acc[2] = {{32896, 32896, 32896, 32896}, {32896, 32896, 32896, 32896}};
 #pragma unroll
                     for (int kc = 0; kc < 2; kc++) {
 #pragma unroll
                         for (int nt = 0; nt < 2; nt++) {
                             const uint2 hv = *(const uint2 *)(HT + (16 * nt + mrow) * HT_STRIDE + 32 * kc + 8 * grp);
-                            const long bv = (long)((((uint64_t)(hv.y ^ 0x80808080u)) << 32) | (hv.x ^ 0x80808080u));
+                            const long bv = (long)((((uint64_t)hv.y) << 32) | hv.x);
                             acc[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)va[kc][mt], bv, acc[nt], 0, 0, 0);
                         }
                     }
 #pragma unroll
-                    for (int nt = 0; nt < 2; nt++) {
-                        uint32_t word = 0;
-#pragma unroll
-                        for (int r = 0; r < 4; r++) word |= (uint32_t)((acc[nt][r] + 32896) >> 8) << (8 * r);
-                        s_b[wave][((16 * nt + mrow) * B_STRIDE + 16 * mt + 4 * grp) >> 2] = word;
-                    }
+                    for (int nt = 0; nt < 2; nt++)
+                        s_b[wave][((16 * nt + mrow) * B_STRIDE + 16 * mt + 4 * grp) >> 2] = pack_byte1(acc[nt]);
                 }
             } else {
                 for (int t = lane; t < 31 * 31; t += 64) {
                     const int c = t / 31, r = t - c * 31;
-                    BT[c * B_STRIDE + r] = R[(r + 3) * R_STRIDE + delta + c + 3];
+                    BT[c * B_STRIDE + r] = R[(r + 3) * R_STRIDE + delta + c + 3] ^ 0x80u;
                 }
             }
         }
@@ -269,9 +306,8 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
             uint32_t words[8];
 #pragma unroll
             for (int rnd = 0; rnd < 4; rnd++) {
-                const char4 q = qv[rnd];
-                const int pa = BT[(15 + q.x) * B_STRIDE + 15 + q.y];
-                const int pb = BT[(15 + q.z) * B_STRIDE + 15 + q.w];
+                const int pa = BT[qv[rnd] & 0xFFFFu];
+                const int pb = BT[qv[rnd] >> 16];
                 const uint64_t bits = __ballot(pa < pb);
                 words[2 * rnd] = (uint32_t)bits;
                 words[2 * rnd + 1] = (uint32_t)(bits >> 32);
@@ -351,6 +387,7 @@ extern "C" int32_t orb_describe(const vsfe_ctx *ctx, const vsfe_batch *b, const 
     a.blur = ctx->p.blur;
     a.aligned0 = b->aligned_input && (((uintptr_t)images & 3) == 0) ? 1 : 0;
     const int64_t slots = b->info.kp_capacity;
+    if (slots >= ((int64_t)1 << 31)) return fail(VSFE_ECAPACITY, "more than 2^31 keypoint slots");
     int64_t blocks = (slots + ORB_WAVES - 1) / ORB_WAVES;
     if (blocks <= 0) return VSFE_OK;
     static const int64_t resident = [] {
@@ -363,7 +400,10 @@ extern "C" int32_t orb_describe(const vsfe_ctx *ctx, const vsfe_batch *b, const 
         return (int64_t)n_cu * per_cu;
     }();
     blocks = std::min(blocks, resident);
+    const int64_t nw = blocks * ORB_WAVES;
+    a.step_img = (int)(nw / a.n_max);
+    a.step_i = (int)(nw % a.n_max);
     hipLaunchKernelGGL(orb_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, b->d_images, images, pyr,
-                       *kps, kp_count, ctx->d_pattern_rot, desc, a, slots);
+                       *kps, kp_count, ctx->d_pattern_off, desc, a);
     return check_launch("orb_describe");
 }

@@ -56,6 +56,10 @@ struct CellChunk {
     uint32_t first;        // cell index within the level
 };
 
+// Byte stride of a column of the smoothed 31 x 31 patch the descriptor tests
+// read: point (u, v) of the pattern is at (15 + u) * ORB_PATCH_STRIDE + 15 + v.
+constexpr int ORB_PATCH_STRIDE = 32;
+
 // Rotation and bin tables (Q14) of the orientation and rBRIEF steps.
 struct OrbTables {
     int32_t bin_x[30], bin_y[30];
@@ -67,7 +71,7 @@ struct vsfe_ctx {
     vsfe_params p;
     int device;
     int tile_w, tile_h;
-    int8_t *d_pattern_rot;     // [30][256][4] rotated test pairs (device)
+    uint32_t *d_pattern_off;   // [30][256] rotated test pairs as patch offsets a | b << 16 (device)
     vsfe::OrbTables tables;    // host copy, passed by value to kernels
     int32_t scale_q16[VSFE_MAX_LEVELS];
     int32_t cell[VSFE_MAX_LEVELS];
