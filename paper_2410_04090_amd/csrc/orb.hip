@@ -49,7 +49,6 @@ constexpr uint32_t W_HI = 49u | (33u << 8) | (18u << 16);
 struct OrbArgs {
     OrbTables tab;
     int n_max, n_images, blur, aligned0;
-    int step_img, step_i;      // one wave's slot stride, as whole images plus slots
 };
 
 // Per disc row v = -15..15: byte u' (u = u' - 15) of 8 words; ones: 1 inside
@@ -106,8 +105,7 @@ __device__ __forceinline__ uint32_t pack_byte1(const i32x4 &a) {
 }
 
 // Persistent waves: a wave takes keypoint slots first, first + W, ... (W =
-// waves in the grid, walked as whole images plus slots so that no division
-// runs in the loop) and loads the next keypoint's neighbourhood into
+// waves in the grid) and loads the next keypoint's neighbourhood into
 // registers while it computes the current one.  The per-lane constant
 // tables are read once, and the current keypoint's pattern is read before
 // the next prefetch is issued, so no wait inside the loop waits for the
@@ -158,45 +156,71 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         t_word[u] = t - 10 * t_row[u];
     }
 
-    // prefetched state of the next keypoint
+    // Keypoint metadata of the wave's next 64 iterations, one iteration per
+    // lane (slot, counts, coordinates, level geometry: three dependent
+    // memory round trips paid once per 64 keypoints instead of once per
+    // keypoint); an iteration reads its lane's values with readlane.
+    const int64_t first = (int64_t)xcd_item(blockIdx.x, gridDim.x) * ORB_WAVES + wave;
+    const int64_t nw = (int64_t)gridDim.x * ORB_WAVES;
+    const int64_t n_slots = (int64_t)a.n_images * a.n_max;
+    uint32_t m_xy = 0, m_wh = 0, m_pitch = 0, m_flags = 0;   // flags: 1 = active, 2 = level 0
+    uint64_t m_off = 0;                                     // level offset in its buffer
+    auto load_meta = [&](int64_t k0) {
+        const int64_t sl = first + (k0 + lane) * nw;
+        m_flags = 0;
+        if (sl < n_slots) {
+            const int image = (int)sl / a.n_max, i = (int)sl - image * a.n_max;
+            if (i < kp_count[image]) {
+                const int x = kps.x[sl], y = kps.y[sl], lvl = kps.level[sl];
+                const LevelDev &lv = imgs[image].lv[lvl];
+                m_xy = (uint32_t)x | ((uint32_t)y << 16);
+                m_wh = (uint32_t)lv.w | ((uint32_t)lv.h << 16);
+                m_pitch = (uint32_t)lv.pitch;
+                m_off = (uint64_t)lv.offset;
+                m_flags = 1u | (lvl == 0 ? 2u : 0u);
+            }
+        }
+    };
+
+    // prefetched state of the next keypoint (iteration j of the metadata batch)
     bool p_act = false;
     int p_delta = 0;
     uint32_t p_v[6];
-    auto fetch = [&](int image, int i) {
-        p_act = image < a.n_images && i < kp_count[image];
+    auto fetch = [&](int j) {
+        const uint32_t fl = __builtin_amdgcn_readlane(m_flags, j);
+        p_act = (fl & 1u) != 0;
         if (!p_act) return;
-        const int64_t s = (int64_t)image * a.n_max + i;
-        const int x = __builtin_amdgcn_readfirstlane((int)kps.x[s]);
-        const int y = __builtin_amdgcn_readfirstlane((int)kps.y[s]);
-        const int lvl = __builtin_amdgcn_readfirstlane((int)kps.level[s]);
-        const LevelDev lv = imgs[image].lv[lvl];
-        const uint8_t *src = (lvl == 0 ? images : pyr) + lv.offset;
-        const bool aligned = lvl > 0 || a.aligned0;
+        const uint32_t xy = __builtin_amdgcn_readlane(m_xy, j), wh = __builtin_amdgcn_readlane(m_wh, j);
+        const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
+        const int lw = (int)(wh & 0xFFFFu), lh = (int)(wh >> 16);
+        const int pitch = (int)__builtin_amdgcn_readlane(m_pitch, j);
+        const int64_t off = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(m_off >> 32), j) << 32) |
+                                      __builtin_amdgcn_readlane((uint32_t)m_off, j));
+        const uint8_t *src = ((fl & 2u) ? images : pyr) + off;
+        const bool aligned = !(fl & 2u) || a.aligned0;
         const int xs = (x - 18) & ~3;
         p_delta = (x - 18) - xs;
-        if (aligned && y >= 18 && y + 18 < lv.h && xs >= 0 && xs + 40 <= lv.w) {
+        if (aligned && y >= 18 && y + 18 < lh && xs >= 0 && xs + 40 <= lw) {
             // the whole 40 x 37 window lies inside the level: plain 32-bit loads
-            const uint8_t *base = src + (int64_t)(y - 18) * lv.pitch + xs;
+            const uint8_t *base = src + (int64_t)(y - 18) * pitch + xs;
 #pragma unroll
             for (int u = 0; u < 6; u++)
-                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const uint32_t *)(base + t_row[u] * lv.pitch + 4 * t_word[u]) : 0u;
+                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const uint32_t *)(base + t_row[u] * pitch + 4 * t_word[u]) : 0u;
         } else {
 #pragma unroll
             for (int u = 0; u < 6; u++) {
                 p_v[u] = 0u;
                 if (lane + 64 * u < 37 * 10) {
-                    const int gy = min(max(y - 18 + t_row[u], 0), lv.h - 1);
-                    p_v[u] = fetch4c(src + (int64_t)gy * lv.pitch, xs + 4 * t_word[u], lv.w);
+                    const int gy = min(max(y - 18 + t_row[u], 0), lh - 1);
+                    p_v[u] = fetch4c(src + (int64_t)gy * pitch, xs + 4 * t_word[u], lw);
                 }
             }
         }
     };
 
-    const int first = xcd_item(blockIdx.x, gridDim.x) * ORB_WAVES + wave;
-    int cimg = first / a.n_max, ci = first - cimg * a.n_max;
-    if (cimg < a.n_images) fetch(cimg, ci);
-
-    while (cimg < a.n_images) {
+    load_meta(0);
+    fetch(0);
+    for (int64_t k = 0; first + k * nw < n_slots; k++) {
         const bool active = p_act;
         const int delta = p_delta;
         if (active) {
@@ -241,15 +265,10 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
 #pragma unroll
             for (int rnd = 0; rnd < 4; rnd++) qv[rnd] = pr[rnd * 64 + lane];
         }
-        const int64_t slot = (int64_t)cimg * a.n_max + ci;
-        cimg += a.step_img;
-        ci += a.step_i;
-        if (ci >= a.n_max) {
-            ci -= a.n_max;
-            cimg++;
-        }
-        if (cimg < a.n_images) fetch(cimg, ci);
-        else p_act = false;
+        const int64_t slot = first + k * nw;
+        const int jn = (int)((k + 1) & 63);
+        if (jn == 0) load_meta(k + 1);
+        fetch(jn);
 
         if (active) {
             if (a.blur) {
@@ -400,9 +419,6 @@ extern "C" int32_t orb_describe(const vsfe_ctx *ctx, const vsfe_batch *b, const 
         return (int64_t)n_cu * per_cu;
     }();
     blocks = std::min(blocks, resident);
-    const int64_t nw = blocks * ORB_WAVES;
-    a.step_img = (int)(nw / a.n_max);
-    a.step_i = (int)(nw % a.n_max);
     hipLaunchKernelGGL(orb_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, b->d_images, images, pyr,
                        *kps, kp_count, ctx->d_pattern_off, desc, a);
     return check_launch("orb_describe");
