@@ -37,7 +37,7 @@
 namespace vsfe {
 
 constexpr int ORB_WAVES = 4;
-constexpr int R_STRIDE = 40;      // staged 37 x 37 neighbourhood, one row per 40 bytes
+constexpr int R_STRIDE = 40;      // staged 37 x 37 neighbourhood, one row per 40 bytes (10 words)
 constexpr int R_BYTES = 48 * R_STRIDE + 32;   // 48 rows (3 MFMA row tiles) + read slack
 constexpr int HT_STRIDE = 48;     // horizontal pass, transposed: [column][row], 37 of 48 rows used
 constexpr int HT_BYTES = 32 * HT_STRIDE + 16;
@@ -59,15 +59,15 @@ struct DiscTables {
 };
 __constant__ DiscTables c_disc;
 
-// Constant MFMA operands of the smoothing (v_mfma_i32_16x16x32_i8, 8 bytes
-// per lane: lane l covers K = 8 (l / 16) .. + 7 of row / column l % 16):
-//  hb[kc][nt][l]: horizontal pass B = K0[j][c] = w[j - c] (j = 32 kc + 8 (l/16) + b,
-//                 c = 16 nt + l % 16), zero outside 0 <= j - c <= 6;
-//  va[kc][mt][l]: vertical pass A = Kv[r'][r] = w[r - r'] (r' = 16 mt + l % 16,
-//                 r = 32 kc + 8 (l/16) + b).
+// Constant MFMA operand of the smoothing (v_mfma_i32_16x16x32_i8, 8 bytes per
+// lane: lane l covers K = 8 (l / 16) .. + 7 of row / column l % 16): the band
+// W[k][n] = w[k - n], zero outside 0 <= k - n <= 6.  A 16-wide output tile
+// starting at index 16 t reads inputs 16 t .. 16 t + 21, so one K chunk of 32
+// starting at 16 t covers it, and relative to that start the band is the same
+// for every tile: it is B of the horizontal pass (K = input column, n =
+// output column) and A of the vertical pass (K = input row, n = output row).
 struct SmoothTables {
-    uint64_t hb[2][2][64];
-    uint64_t va[2][2][64];
+    uint64_t band[64];
 };
 __constant__ SmoothTables c_smooth;
 
@@ -118,43 +118,38 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
     __shared__ __attribute__((aligned(16))) uint32_t s_r[ORB_WAVES][R_BYTES / 4];
     __shared__ __attribute__((aligned(16))) uint32_t s_ht[ORB_WAVES][HT_BYTES / 4];
     __shared__ __attribute__((aligned(16))) uint32_t s_b[ORB_WAVES][B_BYTES / 4];
+    __shared__ __attribute__((aligned(16))) uint32_t s_disc[2 * 31 * 8];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int mrow = lane & 15, grp = lane >> 4;
     uint8_t *R = (uint8_t *)s_r[wave];
     uint8_t *HT = (uint8_t *)s_ht[wave];
     uint8_t *BT = (uint8_t *)s_b[wave];
 
-    // per-lane constants; cS / cT undo the -128 of the staged bytes
-    uint32_t d_ones[8], d_ramp[8];
+    // disc weights in LDS (read per keypoint, not held in registers); cS / cT
+    // undo the -128 of the staged bytes
+    for (int k = threadIdx.x; k < 2 * 31 * 8; k += 256)
+        s_disc[k] = k < 31 * 8 ? (&c_disc.ones[0][0])[k] : (&c_disc.ramp[0][0])[k - 31 * 8];
     int cS = 0, cT = 0;
+    if (lane < 31) {
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
-        d_ones[k] = lane < 31 ? c_disc.ones[lane][k] : 0u;
-        d_ramp[k] = lane < 31 ? c_disc.ramp[lane][k] : 0u;
-        cS += (int)__builtin_amdgcn_udot4(d_ones[k], 0x80808080u, 0u, false);
-        cT += (int)__builtin_amdgcn_udot4(d_ramp[k], 0x80808080u, 0u, false);
-    }
-    uint64_t bh[2][2], va[2][2];
-#pragma unroll
-    for (int kc = 0; kc < 2; kc++)
-#pragma unroll
-        for (int t2 = 0; t2 < 2; t2++) {
-            bh[kc][t2] = c_smooth.hb[kc][t2][lane];
-            va[kc][t2] = c_smooth.va[kc][t2][lane];
+        for (int k = 0; k < 8; k++) {
+            cS += (int)__builtin_amdgcn_udot4(c_disc.ones[lane][k], 0x80808080u, 0u, false);
+            cT += (int)__builtin_amdgcn_udot4(c_disc.ramp[lane][k], 0x80808080u, 0u, false);
         }
+    }
+    __syncthreads();
+    const long band = (long)c_smooth.band[lane];
     int64_t bx = 0, by = 0;
     if (lane < 30) {
         bx = a.tab.bin_x[lane];
         by = a.tab.bin_y[lane];
     }
     // staging tasks of this lane: dword t = lane + 64 u is row t / 10, word t % 10
-    int t_row[6], t_word[6];
+    // (its LDS word is t itself: rows are 10 words apart)
+    static_assert(R_STRIDE == 40, "staging assumes 10 words per row");
+    int t_row[6];
 #pragma unroll
-    for (int u = 0; u < 6; u++) {
-        const int t = lane + 64 * u;
-        t_row[u] = t / 10;
-        t_word[u] = t - 10 * t_row[u];
-    }
+    for (int u = 0; u < 6; u++) t_row[u] = (lane + 64 * u) / 10;
 
     // Keypoint metadata of the wave's next 64 iterations, one iteration per
     // lane (slot, counts, coordinates, level geometry: three dependent
@@ -205,14 +200,14 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
             const uint8_t *base = src + (int64_t)(y - 18) * pitch + xs;
 #pragma unroll
             for (int u = 0; u < 6; u++)
-                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const uint32_t *)(base + t_row[u] * pitch + 4 * t_word[u]) : 0u;
+                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const uint32_t *)(base + t_row[u] * (pitch - 40) + 4 * (lane + 64 * u)) : 0u;
         } else {
 #pragma unroll
             for (int u = 0; u < 6; u++) {
                 p_v[u] = 0u;
                 if (lane + 64 * u < 37 * 10) {
                     const int gy = min(max(y - 18 + t_row[u], 0), lh - 1);
-                    p_v[u] = fetch4c(src + (int64_t)gy * pitch, xs + 4 * t_word[u], lw);
+                    p_v[u] = fetch4c(src + (int64_t)gy * pitch, xs + 4 * (lane + 64 * u - 10 * t_row[u]), lw);
                 }
             }
         }
@@ -226,7 +221,7 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         if (active) {
 #pragma unroll
             for (int u = 0; u < 6; u++)
-                if (lane + 64 * u < 37 * 10) s_r[wave][t_row[u] * (R_STRIDE / 4) + t_word[u]] = p_v[u] ^ 0x80808080u;
+                if (lane + 64 * u < 37 * 10) s_r[wave][lane + 64 * u] = p_v[u] ^ 0x80808080u;
         }
         wave_lds_fence();
 
@@ -241,8 +236,8 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
             for (int k = 0; k < 8; k++) {
                 const uint32_t nxt = w[k + 1];
                 const uint32_t b4 = __builtin_amdgcn_alignbyte(nxt, prev, al);
-                S = __builtin_amdgcn_sdot4((int)b4, (int)d_ones[k], S, false);
-                T = __builtin_amdgcn_sdot4((int)b4, (int)d_ramp[k], T, false);
+                S = __builtin_amdgcn_sdot4((int)b4, (int)s_disc[lane * 8 + k], S, false);
+                T = __builtin_amdgcn_sdot4((int)b4, (int)s_disc[31 * 8 + lane * 8 + k], T, false);
                 prev = nxt;
             }
             m10 = T - 16 * S;
@@ -272,46 +267,39 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
 
         if (active) {
             if (a.blur) {
-                // horizontal pass on MFMA: H[r][c] - 128 = (128 + sum_j R'[r][j] K0[j][c]) >> 8
+                // horizontal pass on MFMA: H[r][c] - 128 = (128 + sum_j R'[r][j] W[j][c]) >> 8
                 // with R'[r][j] = R[r][j + delta] - 128; 3 row tiles x 2 column
-                // tiles x 2 K chunks.  Written transposed, 4 rows per dword.
+                // tiles, one K chunk each (inputs 16 nt .. 16 nt + 31; the band
+                // is zero beyond 16 nt + 21, which also covers the bytes read
+                // past a row's end).  Written transposed, 4 rows per dword.
 #pragma unroll
                 for (int mt = 0; mt < 3; mt++) {
-                    i32x4 acc[2] = {{128, 128, 128, 128}, {128, 128, 128, 128}};
 #pragma unroll
-                    for (int kc = 0; kc < 2; kc++) {
-                        const uint32_t *w = (const uint32_t *)(R + (16 * mt + mrow) * R_STRIDE + 32 * kc + 8 * grp);
+                    for (int nt = 0; nt < 2; nt++) {
+                        const uint32_t *w = (const uint32_t *)(R + (16 * mt + mrow) * R_STRIDE + 16 * nt + 8 * grp);
                         const uint32_t d0 = w[0], d1 = w[1], d2 = w[2];
                         const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, delta);
                         const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, delta);
                         const long av = (long)(((uint64_t)hi << 32) | lo);
-#pragma unroll
-                        for (int nt = 0; nt < 2; nt++)
-                            acc[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8(av, (long)bh[kc][nt], acc[nt], 0, 0, 0);
+                        const i32x4 acc = __builtin_amdgcn_mfma_i32_16x16x32_i8(av, band, i32x4{128, 128, 128, 128}, 0, 0, 0);
+                        *(uint32_t *)(HT + (16 * nt + mrow) * HT_STRIDE + 16 * mt + 4 * grp) = pack_byte1(acc);
                     }
-#pragma unroll
-                    for (int nt = 0; nt < 2; nt++)
-                        *(uint32_t *)(HT + (16 * nt + mrow) * HT_STRIDE + 16 * mt + 4 * grp) = pack_byte1(acc[nt]);
                 }
                 wave_lds_fence();
-                // vertical pass on MFMA: V[r'][c] = (32896 + sum_r Kv[r'][r] (H[r][c] - 128)) >> 8,
-                // B read from the transposed H (8 rows of one column per lane);
-                // the output is written transposed, 4 rows per dword
+                // vertical pass on MFMA: V[r'][c] = (32896 + sum_r W[r][r'] (H[r][c] - 128)) >> 8,
+                // 2 row tiles x 2 column tiles, one K chunk each (rows 16 mt ..
+                // 16 mt + 31), B read from the transposed H (8 rows of one
+                // column per lane); the output is written transposed, 4 rows per dword
 #pragma unroll
                 for (int mt = 0; mt < 2; mt++) {
-                    i32x4 acc[2] = {{32896, 32896, 32896, 32896}, {32896, 32896, 32896, 32896}};
 #pragma unroll
-                    for (int kc = 0; kc < 2; kc++) {
-#pragma unroll
-                        for (int nt = 0; nt < 2; nt++) {
-                            const uint2 hv = *(const uint2 *)(HT + (16 * nt + mrow) * HT_STRIDE + 32 * kc + 8 * grp);
-                            const long bv = (long)((((uint64_t)hv.y) << 32) | hv.x);
-                            acc[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)va[kc][mt], bv, acc[nt], 0, 0, 0);
-                        }
+                    for (int nt = 0; nt < 2; nt++) {
+                        const uint2 hv = *(const uint2 *)(HT + (16 * nt + mrow) * HT_STRIDE + 16 * mt + 8 * grp);
+                        const long bv = (long)((((uint64_t)hv.y) << 32) | hv.x);
+                        const i32x4 acc =
+                            __builtin_amdgcn_mfma_i32_16x16x32_i8(band, bv, i32x4{32896, 32896, 32896, 32896}, 0, 0, 0);
+                        s_b[wave][((16 * nt + mrow) * B_STRIDE + 16 * mt + 4 * grp) >> 2] = pack_byte1(acc);
                     }
-#pragma unroll
-                    for (int nt = 0; nt < 2; nt++)
-                        s_b[wave][((16 * nt + mrow) * B_STRIDE + 16 * mt + 4 * grp) >> 2] = pack_byte1(acc[nt]);
                 }
             } else {
                 for (int t = lane; t < 31 * 31; t += 64) {
@@ -365,20 +353,14 @@ static int32_t upload_disc(int device, hipStream_t st) {
     static const int kw[7] = {18, 33, 49, 56, 49, 33, 18};
     SmoothTables sm;
     memset(&sm, 0, sizeof(sm));
-    for (int kc = 0; kc < 2; kc++)
-        for (int t2 = 0; t2 < 2; t2++)
-            for (int l = 0; l < 64; l++) {
-                uint64_t hb = 0, va = 0;
-                for (int bb = 0; bb < 8; bb++) {
-                    const int k = 32 * kc + 8 * (l >> 4) + bb;
-                    const int dh = k - (16 * t2 + (l & 15));     // j - c
-                    const int dv = k - (16 * t2 + (l & 15));     // r - r'
-                    if (dh >= 0 && dh <= 6) hb |= (uint64_t)kw[dh] << (8 * bb);
-                    if (dv >= 0 && dv <= 6) va |= (uint64_t)kw[dv] << (8 * bb);
-                }
-                sm.hb[kc][t2][l] = hb;
-                sm.va[kc][t2][l] = va;
-            }
+    for (int l = 0; l < 64; l++) {
+        uint64_t band = 0;
+        for (int bb = 0; bb < 8; bb++) {
+            const int d = 8 * (l >> 4) + bb - (l & 15);          // k - n
+            if (d >= 0 && d <= 6) band |= (uint64_t)kw[d] << (8 * bb);
+        }
+        sm.band[l] = band;
+    }
     if (hipMemcpyToSymbol(HIP_SYMBOL(c_smooth), &sm, sizeof(sm), 0, hipMemcpyHostToDevice) != hipSuccess)
         return fail(VSFE_EHIP, "upload of the smoothing tables failed");
     if (device >= 0 && device < 64) g_disc_ready[device] = true;
