@@ -7,10 +7,10 @@
 // exact sum, factored: h = 256 a + fx (b - a), v = 256 h0 + fy (h1 - h0)).
 //
 // One launch per level covers that level of every image.  A block writes a
-// 256 x 16 output tile: it stages the source window (chosen on the host, at
-// most 336 x 24 bytes) in LDS with 16-byte loads and reads per-column and
+// 256 x 32 output tile: it stages the source window (chosen on the host, at
+// most 336 x 44 bytes) in LDS with 16-byte loads and reads per-column and
 // per-row source indices and weights from host-built tables (no division on
-// the device).  Each lane produces 4 columns of its wave's 4 rows, so the
+// the device).  Each lane produces 4 columns of its wave's 8 rows, so the
 // source rows are uniform per wave: every needed source row is lerped
 // horizontally once, two columns per packed 16-bit multiply-add
 // (a (256 - fx) + b fx <= 65280 fits), with the 4 source bytes of a column
@@ -48,19 +48,31 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
     const int tid = threadIdx.x;
     const bool aligned = level > 1 || aligned0;
 
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    constexpr int ROWS = PYR_TH / 4;                     // output rows per wave
+    const int oy0 = it.ty * PYR_TH + ROWS * wave;        // uniform
+    const int ox = it.tx * PYR_TW + 4 * lane;
+    // resampling table entries of the lane's 4 columns and the wave's rows,
+    // loaded together with the staged rows
+    uint32_t ex[4], ey[ROWS];
+#pragma unroll
+    for (int j = 0; j < 4; j++) ex[j] = coord[d.xtab + min(ox + j, d.w - 1)];
+#pragma unroll
+    for (int k = 0; k < ROWS; k++) ey[k] = coord[d.ytab + min(oy0 + k, d.h - 1)];
+
     // stage rows ys .. ys+nrows-1, columns xs .. xs+ncols-1 (clamped to the
-    // level) as 16-byte chunks; all of a thread's loads are issued before any
-    // LDS store so they are in flight together
-    const int cpr = it.ncols >> 4;
-    const int ntask = it.nrows * cpr;
+    // level) as 16-byte chunks, task q = row q / 21, chunk q % 21 (a
+    // constant divisor); all of a thread's loads are issued before any LDS
+    // store so they are in flight together
+    constexpr int CPR = PYR_SW / 16;
     uint4 v[PYR_TASKS];
     int at[PYR_TASKS];
 #pragma unroll
     for (int u = 0; u < PYR_TASKS; u++) {
         const int q = tid + 256 * u;
+        const int rr = q / CPR, k = q - rr * CPR;
         at[u] = -1;
-        if (q < ntask) {
-            const int rr = q / cpr, k = q - rr * cpr;
+        if (rr < (int)it.nrows && 16 * k < (int)it.ncols) {
             const int gy = min((int)it.ys + rr, s.h - 1);
             v[u] = fetch16c(src + (int64_t)gy * s.pitch, (int)it.xs + 16 * k, s.w, aligned);
             at[u] = rr * (PYR_LDS_W / 16) + k;
@@ -71,17 +83,13 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
         if (at[u] >= 0) ((uint4 *)s_src)[at[u]] = v[u];
     __syncthreads();
 
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int oy0 = it.ty * PYR_TH + 4 * wave;           // uniform
     if (oy0 >= d.h) return;
-    const int ox = it.tx * PYR_TW + 4 * lane;
     // columns: source index (window-local) and weight of the lane's 4 outputs
     int o[4], fx[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-        const uint32_t e = coord[d.xtab + min(ox + j, d.w - 1)];
-        o[j] = (int)(e & 0xFFFFu) - (int)it.xs;
-        fx[j] = (int)(e >> 16);
+        o[j] = (int)(ex[j] & 0xFFFFu) - (int)it.xs;
+        fx[j] = (int)(ex[j] >> 16);
     }
     // byte selectors of (a0, a1), (b0, b1), (a2, a3), (b2, b3) within the
     // two dwords at base01 / base23 (0x0c selects a zero byte)
@@ -106,13 +114,14 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
         h01 = A01 * W01 + B01 * F01;
         h23 = A23 * W23 + B23 * F23;
     };
+    uint8_t *out = dst + (int64_t)oy0 * d.pitch + ox;
     int cur = -2;
     pu2 t01, t23, u01, u23;                              // rows cur, cur + 1
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
+    for (int k = 0; k < ROWS; k++) {
         const int oy = oy0 + k;
         if (oy >= d.h) break;                            // uniform
-        const uint32_t e = coord[d.ytab + oy];
+        const uint32_t e = ey[k];
         const int ya = (int)(e & 0xFFFFu) - (int)it.ys;
         const uint32_t fy = e >> 16, wy = 256u - fy;
         if (ya == cur + 1) {                             // slide by one row
@@ -130,12 +139,12 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
         const uint32_t s2 = (uint32_t)t23.x * wy + (uint32_t)u23.x * fy + 32768u;
         const uint32_t s3 = (uint32_t)t23.y * wy + (uint32_t)u23.y * fy + 32768u;
         const uint32_t word = __builtin_amdgcn_perm(s1, s0, 0x0C0C0602u) | (__builtin_amdgcn_perm(s3, s2, 0x0C0C0602u) << 16);
-        uint8_t *out = dst + (int64_t)oy * d.pitch + ox;
         if (ox + 3 < d.w) {
             *(uint32_t *)out = word;
         } else {
             for (int j = 0; ox + j < d.w; j++) out[j] = (uint8_t)(word >> (8 * j));
         }
+        out += d.pitch;
     }
 }
 

@@ -36,9 +36,9 @@ struct ImageDev {
 // resampled from a staged source window of at most PYR_SH x PYR_SW bytes
 // starting at (xs, ys) of the level above (xs and ncols are multiples of 16).
 constexpr int PYR_TW = 256;   // 64 lanes x 4 columns
-constexpr int PYR_TH = 16;    // 4 waves x 4 rows
+constexpr int PYR_TH = 32;    // 4 waves x 8 rows
 constexpr int PYR_SW = 336;
-constexpr int PYR_SH = 24;
+constexpr int PYR_SH = 44;
 struct PyrItem {
     uint16_t image, tx, ty, pad;
     uint16_t xs, ys, ncols, nrows;
