@@ -26,23 +26,35 @@ __device__ __forceinline__ int project_q16(int x, int S, int limit) {
     return v < limit - 1 ? v : limit - 1;
 }
 
-__device__ __forceinline__ bool better(int kl_h, int kr_h, int kl_g, int kr_g, int mode) {
-    if (mode == 0) return kl_h > kl_g || (kl_h == kl_g && kr_h > kr_g);
-    return kl_h > kl_g && kr_h > kr_g;
-}
-
 // FIX2: the host has checked that at every level the window touches at most
 // 2 x 2 cells, so all candidate keys are loaded up front (all levels' loads
 // in flight together) and then accumulated; otherwise cells are visited in
 // a loop per level.
+//
+// A native position receives at most one keypoint per level (projection
+// scales up, so distinct level pixels land on distinct native pixels), so
+// K_l <= 8 and K_r <= 8 * 4095 < 2^15: the pair is kept packed as
+// (K_l << 16) | K_r, which is also the rank and orders lexicographically.
+// Divisions by a level's cell size use a per-level reciprocal,
+// floor(x / c) = (x * (floor(2^20 / c) + 1)) >> 20, exact for 0 <= x < 8192
+// (the largest image side) and c <= 128 (the error, below x / 2^20 < 1/128,
+// stays under 1 / c); cells are at most 32 pixels.
 template <int R, bool FIX2>
 __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restrict__ imgs,
                                                        const CellChunk *__restrict__ chunks,
                                                        const uint32_t *__restrict__ cell_keys,
                                                        uint32_t *__restrict__ rank, int pfa, int nms_mode) {
     constexpr int Q = 2 * R + 1, NS = Q * Q, CENTER = R * Q + R;
+    __shared__ float s_inv[VSFE_MAX_LEVELS];
+    __shared__ uint32_t s_mag[VSFE_MAX_LEVELS];
     const CellChunk ch = chunks[xcd_item(blockIdx.x, gridDim.x)];
     const ImageDev &im = imgs[ch.image];
+    if (threadIdx.x < (unsigned)im.n_levels) {
+        const LevelDev L = im.lv[threadIdx.x];
+        s_inv[threadIdx.x] = 65536.0f / (float)L.scale_q16;
+        s_mag[threadIdx.x] = (1u << 20) / (uint32_t)L.cell + 1u;
+    }
+    __syncthreads();
     const LevelDev lv = im.lv[ch.level];
     const int idx = (int)ch.first + (int)threadIdx.x;
     if (idx >= lv.ncx * lv.ncy) return;
@@ -52,21 +64,22 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
         rank[g] = 0;
         return;
     }
-    const int c = lv.cell, cx = idx % lv.ncx, cy = idx / lv.ncx;
+    const int c = lv.cell, cy = idx / lv.ncx, cx = idx - cy * lv.ncx;
     const int off = 1023 - (int)(key & 1023u);
-    const int x = cx * c + off % c, y = cy * c + off / c;
+    const int oy = (int)(((uint32_t)off * s_mag[ch.level]) >> 20);
+    const int x = cx * c + (off - oy * c), y = cy * c + oy;
     const int score = (int)((key >> 10) & 0xFFFu);
     if (!pfa) {
         rank[g] = (1u << 16) | (uint32_t)score;
         return;
     }
     const int px = project_q16(x, lv.scale_q16, im.w), py = project_q16(y, lv.scale_q16, im.h);
-    int kl[NS], kr[NS];
+    uint32_t acc[NS];
 #pragma unroll
-    for (int s = 0; s < NS; s++) kl[s] = kr[s] = 0;
+    for (int s = 0; s < NS; s++) acc[s] = 0;
     // candidate cells of level m: those whose pixels can project into the window
-    auto window = [&](const LevelDev &L, int *a0, int *a1, int *b0, int *b1) {
-        const float inv = 65536.0f / (float)L.scale_q16;
+    auto window = [&](int m, const LevelDev &L, int *a0, int *a1, int *b0, int *b1) {
+        const float inv = s_inv[m];
         int xlo = (int)floorf(((float)(px - R) - 0.5f) * inv) - 1, xhi = (int)floorf(((float)(px + R) + 0.5f) * inv) + 1;
         int ylo = (int)floorf(((float)(py - R) - 0.5f) * inv) - 1, yhi = (int)floorf(((float)(py + R) + 0.5f) * inv) + 1;
         xlo = max(xlo, 0);
@@ -74,27 +87,25 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
         xhi = min(xhi, L.w - 1);
         yhi = min(yhi, L.h - 1);
         if (xlo > xhi || ylo > yhi) return false;
-        *a0 = xlo / L.cell;
-        *a1 = xhi / L.cell;
-        *b0 = ylo / L.cell;
-        *b1 = yhi / L.cell;
+        const uint32_t mag = s_mag[m];
+        *a0 = (int)(((uint32_t)xlo * mag) >> 20);
+        *a1 = (int)(((uint32_t)xhi * mag) >> 20);
+        *b0 = (int)(((uint32_t)ylo * mag) >> 20);
+        *b1 = (int)(((uint32_t)yhi * mag) >> 20);
         return true;
     };
-    auto add = [&](const LevelDev &L, int aa, int bb, uint32_t k) {
+    auto add = [&](int m, const LevelDev &L, int aa, int bb, uint32_t k) {
         if (!k) return;
         const int cm = L.cell;
         const int o = 1023 - (int)(k & 1023u);
-        const int qx = project_q16(aa * cm + o % cm, L.scale_q16, im.w) - px;
-        const int qy = project_q16(bb * cm + o / cm, L.scale_q16, im.h) - py;
+        const int orow = (int)(((uint32_t)o * s_mag[m]) >> 20);
+        const int qx = project_q16(aa * cm + (o - orow * cm), L.scale_q16, im.w) - px;
+        const int qy = project_q16(bb * cm + orow, L.scale_q16, im.h) - py;
         if (qx < -R || qx > R || qy < -R || qy > R) return;
         const int slot = (qy + R) * Q + (qx + R);
-        const int sc = (int)((k >> 10) & 0xFFFu);
+        const uint32_t v = (1u << 16) | ((k >> 10) & 0xFFFu);
 #pragma unroll
-        for (int s = 0; s < NS; s++)
-            if (s == slot) {
-                kl[s] += 1;
-                kr[s] += sc;
-            }
+        for (int s = 0; s < NS; s++) acc[s] += s == slot ? v : 0u;
     };
     if constexpr (FIX2) {
         uint32_t kk[VSFE_MAX_LEVELS][4];
@@ -106,7 +117,7 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
             if (m < im.n_levels) {
                 const LevelDev L = im.lv[m];
                 int a0, a1, b0, b1;
-                if (window(L, &a0, &a1, &b0, &b1)) {
+                if (window(m, L, &a0, &a1, &b0, &b1)) {
                     ca[m] = a0;
                     cb[m] = b0;
                     const uint32_t *row0 = cell_keys + L.cell_offset + (int64_t)b0 * L.ncx;
@@ -123,26 +134,30 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
             if (m < im.n_levels) {
                 const LevelDev L = im.lv[m];
 #pragma unroll
-                for (int q = 0; q < 4; q++) add(L, ca[m] + (q & 1), cb[m] + (q >> 1), kk[m][q]);
+                for (int q = 0; q < 4; q++) add(m, L, ca[m] + (q & 1), cb[m] + (q >> 1), kk[m][q]);
             }
         }
     } else {
         for (int m = 0; m < im.n_levels; m++) {
             const LevelDev L = im.lv[m];
             int a0, a1, b0, b1;
-            if (!window(L, &a0, &a1, &b0, &b1)) continue;
+            if (!window(m, L, &a0, &a1, &b0, &b1)) continue;
             a1 = min(a1, L.ncx - 1);
             b1 = min(b1, L.ncy - 1);
             for (int bb = b0; bb <= b1; bb++)
-                for (int aa = a0; aa <= a1; aa++) add(L, aa, bb, cell_keys[L.cell_offset + (int64_t)bb * L.ncx + aa]);
+                for (int aa = a0; aa <= a1; aa++) add(m, L, aa, bb, cell_keys[L.cell_offset + (int64_t)bb * L.ncx + aa]);
         }
     }
-    const int kl_own = kl[CENTER], kr_own = kr[CENTER];
+    const uint32_t own = acc[CENTER];
     bool sup = false;
 #pragma unroll
-    for (int s = 0; s < NS; s++)
-        if (s != CENTER && kl[s] > 0 && better(kl[s], kr[s], kl_own, kr_own, nms_mode)) sup = true;
-    rank[g] = sup ? 0u : (((uint32_t)kl_own << 16) | (uint32_t)kr_own);
+    for (int s = 0; s < NS; s++) {
+        if (s == CENTER || acc[s] == 0) continue;
+        // mode 0: (K_l, K_r) lexicographically larger; mode 1: both larger
+        sup = sup || (nms_mode == 0 ? acc[s] > own
+                                    : ((acc[s] >> 16) > (own >> 16) && (acc[s] & 0xFFFFu) > (own & 0xFFFFu)));
+    }
+    rank[g] = sup ? 0u : own;
 }
 
 constexpr int SEL_THREADS = 1024;
