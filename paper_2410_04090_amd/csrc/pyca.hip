@@ -14,8 +14,8 @@
 //   keypoints, 0 for empty or suppressed cells.
 // Kernel 2 (one block per image): if more than n_max survive, a two-pass
 //   radix select finds the n_max-th largest rank T; cells with rank > T and
-//   the first (in canonical order) cells with rank == T are kept; block
-//   prefix sums compact the survivors into the keypoint arrays in canonical
+//   the first (in canonical order) cells with rank == T are kept; a block
+//   prefix sum compacts the survivors into the keypoint arrays in canonical
 //   order (level, cell row, cell column).
 #include "vsfe_internal.h"
 
@@ -162,26 +162,40 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
 
 constexpr int SEL_THREADS = 1024;
 constexpr int SEL_WAVES = SEL_THREADS / 64;
+constexpr int SEL_LDS_CELLS = 24576;      // an image's ranks are cached in LDS up to this many cells
 
-// Exclusive prefix counts of two flags at once (a in the low 16 bits, b in
-// the high 16 bits; chunks hold at most SEL_THREADS cells); *total gets
-// both totals.  Two barriers: every thread must call it.
-__device__ __forceinline__ int block_scan_pair(bool a, bool b, int *wave_cnt, int *total) {
+// Exclusive prefix sums of two per-thread counts over the block; *tot_a /
+// *tot_b get the totals.  Two barriers: every thread must call it.
+__device__ __forceinline__ void block_scan2(int a, int b, int *wave_a, int *wave_b, int *ex_a, int *ex_b, int *tot_a,
+                                            int *tot_b) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t ba = __ballot(a), bb = __ballot(b);
-    const uint64_t below = (1ull << lane) - 1ull;
-    const int in_wave = __popcll(ba & below) | (__popcll(bb & below) << 16);
-    if (lane == 0) wave_cnt[wave] = __popcll(ba) | (__popcll(bb) << 16);
-    __syncthreads();
-    int before = 0, all = 0;
-    for (int w = 0; w < SEL_WAVES; w++) {
-        const int v = wave_cnt[w];
-        before += w < wave ? v : 0;
-        all += v;
+    int ia = a, ib = b;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int va = __shfl_up(ia, d), vb = __shfl_up(ib, d);
+        if (lane >= d) {
+            ia += va;
+            ib += vb;
+        }
+    }
+    if (lane == 63) {
+        wave_a[wave] = ia;
+        wave_b[wave] = ib;
     }
     __syncthreads();
-    *total = all;
-    return before + in_wave;
+    int ba = 0, bb = 0, ta = 0, tb = 0;
+    for (int w = 0; w < SEL_WAVES; w++) {
+        const int xa = wave_a[w], xb = wave_b[w];
+        ba += w < wave ? xa : 0;
+        bb += w < wave ? xb : 0;
+        ta += xa;
+        tb += xb;
+    }
+    __syncthreads();
+    *ex_a = ba + ia - a;
+    *ex_b = bb + ib - b;
+    *tot_a = ta;
+    *tot_b = tb;
 }
 
 // Over the 1024 buckets of hist, from the top: the bucket where the running
@@ -212,97 +226,120 @@ __device__ __forceinline__ void find_bucket(const int *hist, int base, int need,
     __syncthreads();
 }
 
+// One block per image.  The image's ranks are read once (into LDS when
+// they fit); the compaction gives each thread a contiguous run of cells, so
+// one block scan of the per-thread counts places every survivor.
 __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
     const ImageDev *__restrict__ imgs, const uint32_t *__restrict__ cell_keys, const uint32_t *__restrict__ rank,
     vsfe_kp_soa kps, int32_t *__restrict__ kp_count, int n_max, int32_t *status) {
+    __shared__ uint32_t s_rank[SEL_LDS_CELLS];
     __shared__ int hist[1024];
-    __shared__ int wave_cnt[SEL_WAVES];
+    __shared__ int wave_a[SEL_WAVES], wave_b[SEL_WAVES];
     __shared__ int s_sel[3];   // threshold T, count of ranks > T, bucket
     const ImageDev &im = imgs[blockIdx.x];
     const int64_t base = im.cell_base;
     const int n = (int)im.n_cells;
     const int tid = threadIdx.x;
+    const bool cached = n <= SEL_LDS_CELLS;
+    auto rk = [&](int i) { return cached ? s_rank[i] : rank[base + i]; };
 
     // pass 1: histogram of the high 10 bits of the nonzero ranks (ranks <
-    // 2^20); its total is the number of survivors
+    // 2^20); its total is the number of survivors.  Four loads per thread
+    // are in flight at once.
     hist[tid] = 0;
     __syncthreads();
-    for (int i = tid; i < n; i += SEL_THREADS) {
-        const uint32_t v = rank[base + i];
-        if (v) atomicAdd(&hist[v >> 10], 1);
+    for (int i0 = 0; i0 < n; i0 += 4 * SEL_THREADS) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int i = i0 + u * SEL_THREADS + tid;
+            v[u] = i < n ? rank[base + i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int i = i0 + u * SEL_THREADS + tid;
+            if (cached && i < n) s_rank[i] = v[u];
+            if (v[u]) atomicAdd(&hist[v[u] >> 10], 1);
+        }
     }
     __syncthreads();
     {
         const int lane = tid & 63, wave = tid >> 6;
         int v = hist[tid];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) wave_cnt[wave] = v;
+        if (lane == 0) wave_a[wave] = v;
     }
     __syncthreads();
     int m = 0;
-    for (int w = 0; w < SEL_WAVES; w++) m += wave_cnt[w];
+    for (int w = 0; w < SEL_WAVES; w++) m += wave_a[w];
 
     uint32_t T = 0;
     int quota = 0;
     if (m > n_max) {
         // bucket of the n_max-th largest rank, then its low 10 bits
-        find_bucket(hist, 0, n_max, wave_cnt, s_sel, 2, 1);
+        find_bucket(hist, 0, n_max, wave_a, s_sel, 2, 1);
         const int bucket = s_sel[2];
         hist[tid] = 0;
         __syncthreads();
         for (int i = tid; i < n; i += SEL_THREADS) {
-            const uint32_t v = rank[base + i];
+            const uint32_t v = rk(i);
             if (v && (int)(v >> 10) == bucket) atomicAdd(&hist[v & 1023u], 1);
         }
         __syncthreads();
-        find_bucket(hist, s_sel[1], n_max, wave_cnt, s_sel, 0, 1);
+        find_bucket(hist, s_sel[1], n_max, wave_a, s_sel, 0, 1);
         T = (uint32_t)((bucket << 10) | s_sel[0]);
         quota = n_max - s_sel[1];
     }
 
-    // compaction in canonical order: one block scan per chunk counts, before
-    // each cell, the ranks above T (low 16 bits) and equal to T (high 16
-    // bits); a cell's slot is (# above) + min(# equal, quota)
-    int gt_running = 0, eq_running = 0;
-    for (int start = 0; start < n; start += SEL_THREADS) {
-        const int i = start + tid;
-        const uint32_t v = i < n ? rank[base + i] : 0u;
+    // compaction in canonical order: thread t owns cells [t seg, (t+1) seg);
+    // a cell's slot is (# ranks above T before it) + min(# equal to T before
+    // it, quota)
+    const int seg = (n + SEL_THREADS - 1) / SEL_THREADS;
+    const int i0 = min(n, tid * seg), i1 = min(n, i0 + seg);
+    int n_gt = 0, n_eq = 0;
+    for (int i = i0; i < i1; i++) {
+        const uint32_t v = rk(i);
+        n_gt += (v != 0 && v > T) ? 1 : 0;
+        n_eq += (v != 0 && T != 0 && v == T) ? 1 : 0;
+    }
+    int gt_before, eq_before, gt_all, eq_all;
+    block_scan2(n_gt, n_eq, wave_a, wave_b, &gt_before, &eq_before, &gt_all, &eq_all);
+    int l = 0;
+    while (l + 1 < im.n_levels && im.lv[l + 1].cell_offset - base <= i0) l++;
+    for (int i = i0; i < i1; i++) {
+        const uint32_t v = rk(i);
         const bool gt = v != 0 && v > T;
         const bool eq = v != 0 && T != 0 && v == T;
-        int tot;
-        const int before = block_scan_pair(gt, eq, wave_cnt, &tot);
-        const int gt_before = gt_running + (before & 0xFFFF), eq_before = eq_running + (before >> 16);
         const bool keep = gt || (eq && eq_before < quota);
         const int slot = gt_before + min(eq_before, quota);
-        if (keep) {
-            int l = 0;
-            while (l + 1 < im.n_levels && im.lv[l + 1].cell_offset - base <= i) l++;
-            const LevelDev &lv = im.lv[l];
-            const int li = (int)(i - (lv.cell_offset - base));
-            const uint32_t key = cell_keys[base + i];
-            const int c = lv.cell, cx = li % lv.ncx, cy = li / lv.ncx;
-            const int off = 1023 - (int)(key & 1023u);
-            const int x = cx * c + off % c, y = cy * c + off / c;
-            if (slot < n_max) {
-                const int64_t o = im.kp_offset + slot;
-                kps.x[o] = (uint16_t)x;
-                kps.y[o] = (uint16_t)y;
-                kps.level[o] = (uint8_t)l;
-                kps.flags[o] = (key & VSFE_KEY_FALLBACK) ? (uint8_t)VSFE_KP_FALLBACK : (uint8_t)0;
-                kps.score[o] = (uint16_t)((key >> 10) & 0xFFFu);
-                kps.x0[o] = (uint16_t)project_q16(x, lv.scale_q16, im.w);
-                kps.y0[o] = (uint16_t)project_q16(y, lv.scale_q16, im.h);
-                kps.kl[o] = (uint8_t)(v >> 16);
-                kps.kr[o] = v & 0xFFFFu;
-                kps.bin[o] = 0;
-            } else if (status) {
-                atomicOr(status, VSFE_DEV_OVERFLOW);
-            }
+        gt_before += gt ? 1 : 0;
+        eq_before += eq ? 1 : 0;
+        if (!keep) continue;
+        while (l + 1 < im.n_levels && im.lv[l + 1].cell_offset - base <= i) l++;
+        const LevelDev &lv = im.lv[l];
+        const int li = (int)(i - (lv.cell_offset - base));
+        const uint32_t key = cell_keys[base + i];
+        const int c = lv.cell, cy = li / lv.ncx, cx = li - cy * lv.ncx;
+        const int off = 1023 - (int)(key & 1023u);
+        const int oy = off / c;
+        const int x = cx * c + (off - oy * c), y = cy * c + oy;
+        if (slot < n_max) {
+            const int64_t o = im.kp_offset + slot;
+            kps.x[o] = (uint16_t)x;
+            kps.y[o] = (uint16_t)y;
+            kps.level[o] = (uint8_t)l;
+            kps.flags[o] = (key & VSFE_KEY_FALLBACK) ? (uint8_t)VSFE_KP_FALLBACK : (uint8_t)0;
+            kps.score[o] = (uint16_t)((key >> 10) & 0xFFFu);
+            kps.x0[o] = (uint16_t)project_q16(x, lv.scale_q16, im.w);
+            kps.y0[o] = (uint16_t)project_q16(y, lv.scale_q16, im.h);
+            kps.kl[o] = (uint8_t)(v >> 16);
+            kps.kr[o] = v & 0xFFFFu;
+            kps.bin[o] = 0;
+        } else if (status) {
+            atomicOr(status, VSFE_DEV_OVERFLOW);
         }
-        gt_running += tot & 0xFFFF;
-        eq_running += tot >> 16;
     }
-    const int kept = gt_running + min(eq_running, quota);
+    const int kept = gt_all + min(eq_all, quota);
     if (tid == 0) kp_count[blockIdx.x] = kept < n_max ? kept : n_max;
 }
 
