@@ -202,9 +202,10 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
     __shared__ uint8_t s_run[FT_MAX_CELLS];
     __shared__ int s_anyw[4];
 
-    // level-major items in dispatch order: each level spreads over all XCDs
-    // (a contiguous range per XCD would give some XCDs only the heavy level 0)
-    const DetItem it = items[blockIdx.x];
+    // level-major items in dispatch order, in groups of 16 neighbouring
+    // tiles per XCD (shared halo lines hit in that XCD's L2; a contiguous
+    // range per XCD would give some XCDs only the heavy level 0)
+    const DetItem it = items[xcd_group_item<16>(blockIdx.x, gridDim.x)];
     const ImageDev &im = imgs[it.image];
     const LevelDev lv = im.lv[it.level];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

@@ -122,6 +122,20 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
+// XCD-aware order that keeps the dispatch order: groups of G consecutive
+// items rotate over the XCDs (group g runs on XCD g % 8), so every XCD
+// walks through the whole item list at the same pace (no XCD is left with
+// only the heavy first part), while G neighbouring items share one L2.
+// Items past the last whole round of 8 G map to themselves.  A bijection on
+// [0, n).
+template <int G>
+__device__ __forceinline__ int xcd_group_item(int b, int n) {
+    const int full = n / (N_XCD * G) * (N_XCD * G);
+    if (b >= full) return b;
+    const int x = b % N_XCD, k = b / N_XCD;
+    return ((k / G) * N_XCD + x) * G + k % G;
+}
+
 void set_error(const std::string &msg);
 int32_t fail(int32_t code, const std::string &msg);
 int32_t check_launch(const char *what);
