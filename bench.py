@@ -150,10 +150,11 @@ def cpu_baseline(wl, imgs, pattern, budget_s):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    w, h = wl.sizes[0]
+    sizes = sorted(set(wl.sizes[:max(done, 1)]))
+    what = "x".join(map(str, sizes[0])) if len(sizes) == 1 else "mixed sizes"
     return {"value": done / dt, "unit": "stereo pairs/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of the %d pairs (%dx%d), single-threaded plain C oracle, %.1f s"
-                      % (done, n_pairs, w, h, dt)}
+            "sample": "%d of the %d pairs (%s), single-threaded plain C oracle, %.1f s"
+                      % (done, n_pairs, what, dt)}
 
 
 def learned_path(args, fe, sizes, stream, exact_value):
