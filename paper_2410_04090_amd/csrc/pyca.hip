@@ -21,8 +21,10 @@
 
 namespace vsfe {
 
+// x * S approximates the native coordinate times 2^16 (x < 8192 / 1.2^l,
+// S < 65536 * 1.2^l + 1), so it stays below 2^29: a 24-bit multiply.
 __device__ __forceinline__ int project_q16(int x, int S, int limit) {
-    const int v = (int)(((int64_t)x * S + 32768) >> 16);
+    const int v = (int)((__umul24((uint32_t)x, (uint32_t)S) + 32768u) >> 16);
     return v < limit - 1 ? v : limit - 1;
 }
 
@@ -47,6 +49,7 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
     constexpr int Q = 2 * R + 1, NS = Q * Q, CENTER = R * Q + R;
     __shared__ float s_inv[VSFE_MAX_LEVELS];
     __shared__ uint32_t s_mag[VSFE_MAX_LEVELS];
+    __shared__ uint32_t s_acc[NS][256];     // each thread's window sums (thread-private columns)
     const CellChunk ch = chunks[xcd_item(blockIdx.x, gridDim.x)];
     const ImageDev &im = imgs[ch.image];
     if (threadIdx.x < (unsigned)im.n_levels) {
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
     }
     const int c = lv.cell, cy = idx / lv.ncx, cx = idx - cy * lv.ncx;
     const int off = 1023 - (int)(key & 1023u);
-    const int oy = (int)(((uint32_t)off * s_mag[ch.level]) >> 20);
+    const int oy = (int)(__umul24((uint32_t)off, s_mag[ch.level]) >> 20);
     const int x = cx * c + (off - oy * c), y = cy * c + oy;
     const int score = (int)((key >> 10) & 0xFFFu);
     if (!pfa) {
@@ -74,9 +77,11 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
         return;
     }
     const int px = project_q16(x, lv.scale_q16, im.w), py = project_q16(y, lv.scale_q16, im.h);
-    uint32_t acc[NS];
+    // the window sums live in LDS: a hit is one LDS add, not a select over
+    // every window position
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int s = 0; s < NS; s++) acc[s] = 0;
+    for (int s = 0; s < NS; s++) s_acc[s][tid] = 0;
     // candidate cells of level m: those whose pixels can project into the window
     auto window = [&](int m, const LevelDev &L, int *a0, int *a1, int *b0, int *b1) {
         const float inv = s_inv[m];
@@ -88,24 +93,22 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
         yhi = min(yhi, L.h - 1);
         if (xlo > xhi || ylo > yhi) return false;
         const uint32_t mag = s_mag[m];
-        *a0 = (int)(((uint32_t)xlo * mag) >> 20);
-        *a1 = (int)(((uint32_t)xhi * mag) >> 20);
-        *b0 = (int)(((uint32_t)ylo * mag) >> 20);
-        *b1 = (int)(((uint32_t)yhi * mag) >> 20);
+        *a0 = (int)(__umul24((uint32_t)xlo, mag) >> 20);
+        *a1 = (int)(__umul24((uint32_t)xhi, mag) >> 20);
+        *b0 = (int)(__umul24((uint32_t)ylo, mag) >> 20);
+        *b1 = (int)(__umul24((uint32_t)yhi, mag) >> 20);
         return true;
     };
     auto add = [&](int m, const LevelDev &L, int aa, int bb, uint32_t k) {
         if (!k) return;
         const int cm = L.cell;
         const int o = 1023 - (int)(k & 1023u);
-        const int orow = (int)(((uint32_t)o * s_mag[m]) >> 20);
-        const int qx = project_q16(aa * cm + (o - orow * cm), L.scale_q16, im.w) - px;
-        const int qy = project_q16(bb * cm + orow, L.scale_q16, im.h) - py;
+        const int orow = (int)(__umul24((uint32_t)o, s_mag[m]) >> 20);
+        const int qx = project_q16(__umul24(aa, cm) + (o - __umul24(orow, cm)), L.scale_q16, im.w) - px;
+        const int qy = project_q16(__umul24(bb, cm) + orow, L.scale_q16, im.h) - py;
         if (qx < -R || qx > R || qy < -R || qy > R) return;
         const int slot = (qy + R) * Q + (qx + R);
-        const uint32_t v = (1u << 16) | ((k >> 10) & 0xFFFu);
-#pragma unroll
-        for (int s = 0; s < NS; s++) acc[s] += s == slot ? v : 0u;
+        atomicAdd(&s_acc[slot][tid], (1u << 16) | ((k >> 10) & 0xFFFu));
     };
     if constexpr (FIX2) {
         uint32_t kk[VSFE_MAX_LEVELS][4];
@@ -120,7 +123,7 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
                 if (window(m, L, &a0, &a1, &b0, &b1)) {
                     ca[m] = a0;
                     cb[m] = b0;
-                    const uint32_t *row0 = cell_keys + L.cell_offset + (int64_t)b0 * L.ncx;
+                    const uint32_t *row0 = cell_keys + L.cell_offset + __umul24(b0, L.ncx);
                     const bool ax = a0 + 1 < L.ncx, by = b0 + 1 < L.ncy;
                     kk[m][0] = row0[a0];
                     if (ax) kk[m][1] = row0[a0 + 1];
@@ -148,14 +151,14 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
                 for (int aa = a0; aa <= a1; aa++) add(m, L, aa, bb, cell_keys[L.cell_offset + (int64_t)bb * L.ncx + aa]);
         }
     }
-    const uint32_t own = acc[CENTER];
+    const uint32_t own = s_acc[CENTER][tid];
     bool sup = false;
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-        if (s == CENTER || acc[s] == 0) continue;
+        const uint32_t a = s_acc[s][tid];
+        if (s == CENTER || a == 0) continue;
         // mode 0: (K_l, K_r) lexicographically larger; mode 1: both larger
-        sup = sup || (nms_mode == 0 ? acc[s] > own
-                                    : ((acc[s] >> 16) > (own >> 16) && (acc[s] & 0xFFFFu) > (own & 0xFFFFu)));
+        sup = sup || (nms_mode == 0 ? a > own : ((a >> 16) > (own >> 16) && (a & 0xFFFFu) > (own & 0xFFFFu)));
     }
     rank[g] = sup ? 0u : own;
 }
