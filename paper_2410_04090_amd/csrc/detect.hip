@@ -39,12 +39,14 @@ namespace vsfe {
 
 constexpr int FT_HALF = 64;                      // lanes per row; lane owns cols l and l + 64
 constexpr int FT_CHUNKS = 6;                     // 16-byte source chunks per row and half
-// LDS words per row: the 6 staged 16-byte chunks of each half (96 words)
-constexpr int FT_W = 96;
+// LDS words per row: the 6 staged 16-byte chunks of each half (96 words),
+// padded to 100 so that successive rows start 4 banks apart (fewer bank
+// conflicts when a wave's candidates sit in the same columns of different rows)
+constexpr int FT_W = 100;
 constexpr int FT_MAX_ROWS = 32;
 constexpr int FT_ROWS = FT_MAX_ROWS + 6;
 constexpr int FT_MAX_CELLS = 128;               // at most 32 x 4 cells per tile
-constexpr int FT_QW = 512;                                // one wave's candidate queue (more: in rounds)
+constexpr int FT_QW = 448;                                // one wave's candidate queue (more: in rounds)
 
 struct DetParams {
     int eps_hi, eps_lo, p_min, p_max, border, eps_min, aligned;
