@@ -39,7 +39,7 @@ namespace vsfe {
 constexpr int ORB_WAVES = 4;
 constexpr int R_STRIDE = 40;      // staged 37 x 37 neighbourhood, one row per 40 bytes (10 words)
 constexpr int R_BYTES = 48 * R_STRIDE + 32;   // 48 rows (3 MFMA row tiles) + read slack
-constexpr int HT_STRIDE = 48;     // horizontal pass, transposed: [column][row], 37 of 48 rows used
+constexpr int HT_STRIDE = 56;     // horizontal pass, transposed: [column][row], 37 of 48 rows used (14 words: columns spread over the banks)
 constexpr int HT_BYTES = 32 * HT_STRIDE + 16;
 constexpr int B_STRIDE = ORB_PATCH_STRIDE;   // final smoothed patch, transposed: [column][row], 31 used
 constexpr int B_BYTES = 32 * B_STRIDE;

@@ -58,7 +58,7 @@ struct CellChunk {
 
 // Byte stride of a column of the smoothed 31 x 31 patch the descriptor tests
 // read: point (u, v) of the pattern is at (15 + u) * ORB_PATCH_STRIDE + 15 + v.
-constexpr int ORB_PATCH_STRIDE = 32;
+constexpr int ORB_PATCH_STRIDE = 36;
 
 // Rotation and bin tables (Q14) of the orientation and rBRIEF steps.
 struct OrbTables {
