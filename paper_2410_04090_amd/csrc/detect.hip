@@ -18,7 +18,9 @@
 //     32-bit word at (row, col) holds pixel col of the left 64-pixel half in
 //     its low 16 bits and pixel col + 64 in its high 16 bits, so any ring
 //     offset of a lane's two pixels is one aligned 32-bit LDS read.  Rows
-//     are fetched as 32-bit words and split with v_perm.
+//     are fetched as 16-byte chunks (one per half per thread, all in flight
+//     together) and split with v_perm; the run flags of the learned gate
+//     are loaded with them.
 //  2. Prefilter every pixel pair with packed 16-bit min / max / saturating
 //     subtract: a cyclic run of >= 9 ring pixels covers two adjacent compass
 //     pixels (0, 4, 8, 12), i.e. one of {0, 8} and one of {4, 12}, so a
@@ -27,10 +29,13 @@
 //  3. Each lane collects its candidates in a bit mask over its rows; a wave
 //     prefix sum of the counts on the DPP network places them in the wave's
 //     own LDS queue, so the full ring test runs densely over candidates only
-//     and no block barrier is needed until the cell keys are reduced (the
-//     screen re-derives the polarity from the same compass test): masks are built with alignbit
-//     (one op inserts one sign bit; run lengths do not depend on bit order)
-//     and runs are tested by shift-and doubling.
+//     and no block barrier is needed until the cell keys are reduced.  The
+//     screen (a run >= p_min at the weaker threshold, polarity re-derived
+//     from the same compass test) compacts its survivors in place; the
+//     decision at both thresholds and the response run on the survivors.
+//     Ring masks are built with alignbit (one op inserts one sign bit; run
+//     lengths do not depend on bit order) and runs are tested by shift-and
+//     doubling.
 //  4. Keys reduce per cell with LDS atomicMax (order independent, so the
 //     result is exact and deterministic) and are written once per cell.
 #include "vsfe_internal.h"
