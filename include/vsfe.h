@@ -231,6 +231,17 @@ int32_t fast_br_detect(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *
                        const uint8_t *pyr, const uint8_t *cell_mask, uint32_t *cell_keys,
                        uint16_t *crf_debug, int32_t *status, void *stream);
 
+/* fast_br_detect restricted to levels level_begin <= l < level_end (same
+ * results for those levels' cells, other cells untouched), without the
+ * response dump.  Level 0 reads only the input, so its detection can run on
+ * a second stream while pyramid_build writes the other levels; calls with
+ * disjoint level ranges write disjoint cells and may run concurrently.
+ * pyr may be null when the range is level 0 only.  Errors: EINVAL (null
+ * pointers, an empty or out-of-range level range), EHIP. */
+int32_t fast_br_detect_levels(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
+                              const uint8_t *pyr, const uint8_t *cell_mask, uint32_t *cell_keys,
+                              int32_t level_begin, int32_t level_end, int32_t *status, void *stream);
+
 /* Sec. II-C-2 (PFA): projection of every culled keypoint to the native
  * scale (x0 = round(x * 1.2^l) in Q16), K_l / K_r per native position,
  * sparse (2r+1)^2 NMS around keypoints, survivors kept at every level, then

@@ -129,8 +129,10 @@ __device__ __forceinline__ bool cell_runs(const uint8_t *mask0, const LevelDev &
 __global__ __launch_bounds__(256) void expand_mask_kernel(const ImageDev *__restrict__ imgs,
                                                           const CellChunk *__restrict__ chunks,
                                                           const uint8_t *__restrict__ mask0,
-                                                          uint8_t *__restrict__ run) {
+                                                          uint8_t *__restrict__ run, int level_begin,
+                                                          int level_end) {
     const CellChunk ch = chunks[blockIdx.x];
+    if (ch.level < level_begin || ch.level >= level_end) return;
     const ImageDev &im = imgs[ch.image];
     const LevelDev lv = im.lv[ch.level];
     const int idx = (int)ch.first + (int)threadIdx.x;
@@ -531,6 +533,26 @@ int32_t detect_launch(const vsfe_ctx *ctx, const vsfe_batch *b, const DetItem *i
     return check_launch("fast_br_detect");
 }
 
+// Gate expansion (if a mask is given) and the detector over the items of
+// levels [lb, le).
+static int32_t detect_range(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images, const uint8_t *pyr,
+                            const uint8_t *cell_mask, uint32_t *cell_keys, uint16_t *crf_debug, int lb, int le,
+                            hipStream_t st) {
+    const uint8_t *run = nullptr;
+    if (cell_mask) {
+        if (!b->d_run) return fail(VSFE_EINVAL, "batch has no run-flag table");
+        if (b->n_chunks > 0) {
+            hipLaunchKernelGGL(expand_mask_kernel, dim3(b->n_chunks), dim3(PYCA_CHUNK), 0, st, b->d_images,
+                               b->d_chunks, cell_mask, b->d_run, lb, le);
+            const int32_t rc = check_launch("fast_br_detect (mask expansion)");
+            if (rc) return rc;
+        }
+        run = b->d_run;
+    }
+    const int i0 = b->det_start[lb], i1 = b->det_start[le];
+    return detect_launch(ctx, b, b->d_det_items + i0, i1 - i0, images, pyr, run, cell_keys, crf_debug, st);
+}
+
 }  // namespace vsfe
 
 using namespace vsfe;
@@ -547,16 +569,17 @@ extern "C" int32_t fast_br_detect(const vsfe_ctx *ctx, const vsfe_batch *b, cons
         rc = check_launch("fast_br_detect (response dump fill)");
         if (rc) return rc;
     }
-    const uint8_t *run = nullptr;
-    if (cell_mask) {
-        if (!b->d_run) return fail(VSFE_EINVAL, "batch has no run-flag table");
-        if (b->n_chunks > 0) {
-            hipLaunchKernelGGL(expand_mask_kernel, dim3(b->n_chunks), dim3(PYCA_CHUNK), 0, st, b->d_images,
-                               b->d_chunks, cell_mask, b->d_run);
-            rc = check_launch("fast_br_detect (mask expansion)");
-            if (rc) return rc;
-        }
-        run = b->d_run;
-    }
-    return detect_launch(ctx, b, b->d_det_items, b->n_det_items, images, pyr, run, cell_keys, crf_debug, st);
+    return detect_range(ctx, b, images, pyr, cell_mask, cell_keys, crf_debug, 0, b->info.n_levels, st);
+}
+
+extern "C" int32_t fast_br_detect_levels(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
+                                         const uint8_t *pyr, const uint8_t *cell_mask, uint32_t *cell_keys,
+                                         int32_t level_begin, int32_t level_end, int32_t *status, void *stream) {
+    int32_t rc = check_common(ctx, b, status);
+    if (rc) return rc;
+    if (level_begin < 0 || level_end > b->info.n_levels || level_begin >= level_end)
+        return fail(VSFE_EINVAL, "level range out of range or empty");
+    if (!images || !cell_keys || (!pyr && level_end > 1)) return fail(VSFE_EINVAL, "null buffer");
+    return detect_range(ctx, b, images, pyr, cell_mask, cell_keys, nullptr, level_begin, level_end,
+                        (hipStream_t)stream);
 }

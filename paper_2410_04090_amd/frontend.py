@@ -66,6 +66,7 @@ class Frontend:
         self.describe = True
         self.stereo = self.n % 2 == 0 and all(self.sizes[i] == self.sizes[i + 1] for i in range(0, self.n, 2))
         self._graph = None
+        self._side_stream = None
 
     # ------------------------------------------------------------ data in/out
     def pack(self, imgs) -> torch.Tensor:
@@ -84,12 +85,31 @@ class Frontend:
         return vsfe.batch_level_info(self.batch, i, l)
 
     # ------------------------------------------------------------ pipeline
-    def run(self, stream=None, mask=None, describe=None, stereo=None):
+    def _side(self):
+        if self._side_stream is None:
+            self._side_stream = torch.cuda.Stream(device=self.device)
+        return self._side_stream
+
+    def run(self, stream=None, mask=None, describe=None, stereo=None, overlap=True):
+        """The exact path.  With `overlap` (and no gate or response dump)
+        level-0 detection, which reads only the input, runs on a second
+        stream while the pyramid is built; the two branches join before the
+        aggregation (also inside a captured graph)."""
         describe = self.describe if describe is None else describe
         stereo = self.stereo if stereo is None else stereo
         c, b = self.ctx, self.batch
-        vsfe.pyramid_build(c, b, self.images, self.pyr, self.status, stream)
-        vsfe.fast_br_detect(c, b, self.images, self.pyr, mask, self.cell_keys, self.crf, self.status, stream)
+        L = self.params.n_levels
+        if overlap and mask is None and self.crf is None and L > 1:
+            st = stream if stream is not None else torch.cuda.current_stream()
+            side = self._side()
+            side.wait_stream(st)
+            vsfe.fast_br_detect_levels(c, b, self.images, self.pyr, None, self.cell_keys, 0, 1, self.status, side)
+            vsfe.pyramid_build(c, b, self.images, self.pyr, self.status, st)
+            vsfe.fast_br_detect_levels(c, b, self.images, self.pyr, None, self.cell_keys, 1, L, self.status, st)
+            st.wait_stream(side)
+        else:
+            vsfe.pyramid_build(c, b, self.images, self.pyr, self.status, stream)
+            vsfe.fast_br_detect(c, b, self.images, self.pyr, mask, self.cell_keys, self.crf, self.status, stream)
         vsfe.pyca_cull_aggregate(c, b, self.cell_keys, self.workspace, self.kps, self.kp_count, self.status,
                                  stream)
         if describe:

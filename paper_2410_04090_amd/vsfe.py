@@ -77,8 +77,8 @@ class TuneReport(C.Structure):
 EXPORTS = ["vsfe_params_default", "vsfe_params_check", "vsfe_level_geometry", "vsfe_ctx_create",
            "vsfe_ctx_destroy", "vsfe_batch_create", "vsfe_batch_destroy", "vsfe_batch_plan",
            "vsfe_batch_info_get", "vsfe_batch_level_info", "vsfe_ctx_set_tile", "vsfe_last_error",
-           "pyramid_build", "fast_br_detect", "pyca_cull_aggregate", "orb_describe", "stereo_match",
-           "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step",
+           "pyramid_build", "fast_br_detect", "fast_br_detect_levels", "pyca_cull_aggregate", "orb_describe",
+           "stereo_match", "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step",
            "vsfe_batch_tiles_get", "vsfe_batch_set_tiles", "vsfe_batch_autotune"]
 
 _lib = None
@@ -126,6 +126,7 @@ def lib():
     L.vsfe_last_error.restype = C.c_char_p
     L.pyramid_build.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fast_br_detect.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.fast_br_detect_levels.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, vp]
     L.pyca_cull_aggregate.argtypes = [vp, vp, vp, vp, C.POINTER(KpSoa), vp, vp, vp]
     L.orb_describe.argtypes = [vp, vp, vp, vp, C.POINTER(KpSoa), vp, vp, vp, vp]
     L.stereo_match.argtypes = [vp, vp, C.POINTER(KpSoa), vp, vp, vp, vp, vp, vp, vp]
@@ -134,8 +135,8 @@ def lib():
     L.cnn_propose.argtypes = [vp, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp]
     L.cnn_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_float, vp, vp, vp, vp]
     L.cnn_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]
-    for f in ("pyramid_build", "fast_br_detect", "pyca_cull_aggregate", "orb_describe", "stereo_match",
-              "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step"):
+    for f in ("pyramid_build", "fast_br_detect", "fast_br_detect_levels", "pyca_cull_aggregate", "orb_describe",
+              "stereo_match", "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -269,6 +270,11 @@ def pyramid_build(ctx, b, images, pyr, status, stream=None):
 def fast_br_detect(ctx, b, images, pyr, cell_mask, cell_keys, crf_debug, status, stream=None):
     _check(lib().fast_br_detect(ctx, b, _p(images), _p(pyr), _p(cell_mask), _p(cell_keys),
                                 _p(crf_debug), _p(status), _stream(stream)))
+
+
+def fast_br_detect_levels(ctx, b, images, pyr, cell_mask, cell_keys, level_begin, level_end, status, stream=None):
+    _check(lib().fast_br_detect_levels(ctx, b, _p(images), _p(pyr), _p(cell_mask), _p(cell_keys), int(level_begin),
+                                       int(level_end), _p(status), _stream(stream)))
 
 
 def pyca_cull_aggregate(ctx, b, cell_keys, workspace, kps, kp_count, status, stream=None):

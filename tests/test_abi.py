@@ -98,3 +98,9 @@ def test_autotune_and_tiles_reject_null_arguments():
     assert lib.vsfe_batch_set_tiles(None, w, w) == vsfe.EINVAL
     assert lib.vsfe_batch_tiles_get(None, w, w) == vsfe.EINVAL
     assert b"null" in lib.vsfe_last_error()
+
+
+def test_detect_levels_rejects_null_arguments():
+    lib = vsfe.lib()
+    assert lib.fast_br_detect_levels(None, None, None, None, None, None, 0, 1, None, None) == vsfe.EINVAL
+    assert b"null" in lib.vsfe_last_error()

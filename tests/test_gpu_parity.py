@@ -179,3 +179,39 @@ def test_graph_replay_matches_eager(fe_mod, pattern):
                 assert np.array_equal(a, b)
     finally:
         fe.close()
+
+
+def test_level_ranges_match_full_detection(fe_mod, pattern):
+    """fast_br_detect_levels over disjoint level ranges, two of them running
+    concurrently on different streams, writes exactly the cell keys of the
+    full call; empty or out-of-range ranges are rejected."""
+    import torch
+    from paper_2410_04090_amd import vsfe
+    imgs = []
+    for k, (w, h) in enumerate([(640, 360), (333, 201)]):
+        imgs += list(scenes.stereo_pair(700 + k, w, h, 100, 30))
+    p = Params()
+    fe = fe_mod.Frontend(p, [(im.shape[1], im.shape[0]) for im in imgs], pattern)
+    try:
+        fe.upload(imgs)
+        c, b, L = fe.ctx, fe.batch, p.n_levels
+        vsfe.pyramid_build(c, b, fe.images, fe.pyr, fe.status)
+        vsfe.fast_br_detect(c, b, fe.images, fe.pyr, None, fe.cell_keys, None, fe.status)
+        torch.cuda.synchronize()
+        full = fe.cell_keys.cpu().numpy().copy()
+        for cut in (1, 3):
+            fe.cell_keys.fill_(-1)
+            main = torch.cuda.current_stream()
+            side = torch.cuda.Stream()
+            side.wait_stream(main)
+            vsfe.fast_br_detect_levels(c, b, fe.images, fe.pyr, None, fe.cell_keys, 0, cut, fe.status, side)
+            vsfe.fast_br_detect_levels(c, b, fe.images, fe.pyr, None, fe.cell_keys, cut, L, fe.status, main)
+            main.wait_stream(side)
+            torch.cuda.synchronize()
+            assert np.array_equal(fe.cell_keys.cpu().numpy(), full), cut
+        assert int(fe.status.item()) == 0
+        for lo, hi in ((2, 2), (-1, 1), (0, L + 1), (3, 1)):
+            with pytest.raises(vsfe.VsfeError):
+                vsfe.fast_br_detect_levels(c, b, fe.images, fe.pyr, None, fe.cell_keys, lo, hi, fe.status)
+    finally:
+        fe.close()
