@@ -51,13 +51,19 @@ struct OrbArgs {
     int n_max, n_images, blur, aligned0;
 };
 
-// Per disc row v = -15..15: byte u' (u = u' - 15) of 8 words; ones: 1 inside
-// the disc, ramp: (u + 16) inside the disc, 0 elsewhere (and at u' = 31).
+// Per disc row v = -15..15: byte u' (u = u' - 15) of 8 words is 0xff inside
+// the disc u^2 + v^2 <= 225, 0 elsewhere (and at u' = 31).  A row's masked
+// bytes dotted with 1 give S_v, dotted with the ramp u' + 1 = u + 16 (the
+// same for every row: bytes 4k + 1 .. 4k + 4 of word k) give T_v.
 struct DiscTables {
-    uint32_t ones[31][8];
-    uint32_t ramp[31][8];
+    uint32_t mask[31][8];
 };
 __constant__ DiscTables c_disc;
+
+__host__ __device__ constexpr uint32_t ramp_word(int k) {
+    return (uint32_t)(4 * k + 1) | ((uint32_t)(4 * k + 2) << 8) | ((uint32_t)(4 * k + 3) << 16) |
+           ((uint32_t)(4 * k + 4) << 24);
+}
 
 // Constant MFMA operand of the smoothing (v_mfma_i32_16x16x32_i8, 8 bytes per
 // lane: lane l covers K = 8 (l / 16) .. + 7 of row / column l % 16): the band
@@ -118,23 +124,22 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
     __shared__ __attribute__((aligned(16))) uint32_t s_r[ORB_WAVES][R_BYTES / 4];
     __shared__ __attribute__((aligned(16))) uint32_t s_ht[ORB_WAVES][HT_BYTES / 4];
     __shared__ __attribute__((aligned(16))) uint32_t s_b[ORB_WAVES][B_BYTES / 4];
-    __shared__ __attribute__((aligned(16))) uint32_t s_disc[2 * 31 * 8];
+    __shared__ __attribute__((aligned(16))) uint32_t s_disc[31 * 8];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int mrow = lane & 15, grp = lane >> 4;
     uint8_t *R = (uint8_t *)s_r[wave];
     uint8_t *HT = (uint8_t *)s_ht[wave];
     uint8_t *BT = (uint8_t *)s_b[wave];
 
-    // disc weights in LDS (read per keypoint, not held in registers); cS / cT
+    // disc masks in LDS (read per keypoint, not held in registers); cS / cT
     // undo the -128 of the staged bytes
-    for (int k = threadIdx.x; k < 2 * 31 * 8; k += 256)
-        s_disc[k] = k < 31 * 8 ? (&c_disc.ones[0][0])[k] : (&c_disc.ramp[0][0])[k - 31 * 8];
+    for (int k = threadIdx.x; k < 31 * 8; k += 256) s_disc[k] = (&c_disc.mask[0][0])[k];
     int cS = 0, cT = 0;
     if (lane < 31) {
 #pragma unroll
         for (int k = 0; k < 8; k++) {
-            cS += (int)__builtin_amdgcn_udot4(c_disc.ones[lane][k], 0x80808080u, 0u, false);
-            cT += (int)__builtin_amdgcn_udot4(c_disc.ramp[lane][k], 0x80808080u, 0u, false);
+            cS += (int)__builtin_amdgcn_udot4(c_disc.mask[lane][k] & 0x01010101u, 0x80808080u, 0u, false);
+            cT += (int)__builtin_amdgcn_udot4(c_disc.mask[lane][k] & ramp_word(k), 0x80808080u, 0u, false);
         }
     }
     __syncthreads();
@@ -236,8 +241,9 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
             for (int k = 0; k < 8; k++) {
                 const uint32_t nxt = w[k + 1];
                 const uint32_t b4 = __builtin_amdgcn_alignbyte(nxt, prev, al);
-                S = __builtin_amdgcn_sdot4((int)b4, (int)s_disc[lane * 8 + k], S, false);
-                T = __builtin_amdgcn_sdot4((int)b4, (int)s_disc[31 * 8 + lane * 8 + k], T, false);
+                const int xm = (int)(b4 & s_disc[lane * 8 + k]);
+                S = __builtin_amdgcn_sdot4(xm, 0x01010101, S, false);
+                T = __builtin_amdgcn_sdot4(xm, (int)ramp_word(k), T, false);
                 prev = nxt;
             }
             m10 = T - 16 * S;
@@ -343,8 +349,7 @@ static int32_t upload_disc(int device, hipStream_t st) {
         for (int ui = 0; ui < 31; ui++) {
             const int u = ui - 15;
             if (u * u + v * v > 225) continue;
-            t.ones[vi][ui >> 2] |= 1u << (8 * (ui & 3));
-            t.ramp[vi][ui >> 2] |= (uint32_t)(u + 16) << (8 * (ui & 3));
+            t.mask[vi][ui >> 2] |= 0xFFu << (8 * (ui & 3));
         }
     }
     (void)st;

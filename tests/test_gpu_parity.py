@@ -93,6 +93,14 @@ def test_ragged_and_tiny_sizes(fe_mod, pattern, W, H):
     run_and_compare(fe_mod, [l, r], Params(), pattern)
 
 
+@pytest.mark.parametrize("W,H", [(97, 61), (640, 17), (1241, 376)])
+def test_overlapped_path_sizes(fe_mod, pattern, W, H):
+    """The default run (level-0 detection on a second stream beside the
+    pyramid build) against the oracle, down to levels with no cell."""
+    l, r = scenes.stereo_pair(90 + W, W, H, 40, 12)
+    run_and_compare(fe_mod, [l, r], Params(), pattern, full_stages=False)
+
+
 def test_flat_images_no_keypoints(fe_mod, pattern):
     img = np.full((120, 160), 128, np.uint8)
     _, refs, _ = run_and_compare(fe_mod, [img, img.copy()], Params(), pattern)
