@@ -93,6 +93,14 @@ def test_ragged_and_tiny_sizes(fe_mod, pattern, W, H):
     run_and_compare(fe_mod, [l, r], Params(), pattern)
 
 
+@pytest.mark.parametrize("W,H", [(8192, 160), (160, 8192)])
+def test_maximum_side(fe_mod, pattern, W, H):
+    """Images at the largest supported side (8192): 16-bit coordinates,
+    projections and cell reciprocals at their range limits."""
+    l, r = scenes.stereo_pair(77 + W, W, H, 300, 64)
+    run_and_compare(fe_mod, [l, r], Params(), pattern, full_stages=False)
+
+
 @pytest.mark.parametrize("W,H", [(97, 61), (640, 17), (1241, 376)])
 def test_overlapped_path_sizes(fe_mod, pattern, W, H):
     """The default run (level-0 detection on a second stream beside the
