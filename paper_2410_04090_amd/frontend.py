@@ -90,13 +90,21 @@ class Frontend:
             self._side_stream = torch.cuda.Stream(device=self.device)
         return self._side_stream
 
-    def run(self, stream=None, mask=None, describe=None, stereo=None, overlap=True):
-        """The exact path.  With `overlap` (and no gate or response dump)
-        level-0 detection, which reads only the input, runs on a second
+    # below this many level-0 pixels in a batch the second branch's
+    # synchronisation costs more than the overlap saves (one 1241 x 376 pair
+    # loses about 20 us, 32 mixed pairs gain)
+    OVERLAP_MIN_PIXELS = 4_000_000
+
+    def run(self, stream=None, mask=None, describe=None, stereo=None, overlap=None):
+        """The exact path.  With `overlap` (default: batches of at least
+        OVERLAP_MIN_PIXELS level-0 pixels; never with a gate or a response
+        dump) level-0 detection, which reads only the input, runs on a second
         stream while the pyramid is built; the two branches join before the
         aggregation (also inside a captured graph)."""
         describe = self.describe if describe is None else describe
         stereo = self.stereo if stereo is None else stereo
+        if overlap is None:
+            overlap = sum(w * h for w, h in self.sizes) >= self.OVERLAP_MIN_PIXELS
         c, b = self.ctx, self.batch
         L = self.params.n_levels
         if overlap and mask is None and self.crf is None and L > 1:

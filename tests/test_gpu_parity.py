@@ -27,7 +27,8 @@ def fe_mod():
     return frontend
 
 
-def run_and_compare(fe_mod, imgs, params, pattern, full_stages=True, tile=None, mask=None, describe=True):
+def run_and_compare(fe_mod, imgs, params, pattern, full_stages=True, tile=None, mask=None, describe=True,
+                    overlap=None):
     sizes = [(im.shape[1], im.shape[0]) for im in imgs]
     say("case: sizes=%s params=%s tile=%s mask=%s" % (sizes[:4], params, tile, mask is not None))
     fe = fe_mod.Frontend(params, sizes, pattern, tile=tile, with_crf=full_stages,
@@ -39,7 +40,7 @@ def run_and_compare(fe_mod, imgs, params, pattern, full_stages=True, tile=None, 
             import torch
             fe.cell_mask.copy_(torch.from_numpy(np.concatenate([m.reshape(-1) for m in mask])))
             mt = fe.cell_mask
-        fe.run(mask=mt, describe=describe and params.border >= 15)
+        fe.run(mask=mt, describe=describe and params.border >= 15, overlap=overlap)
         import torch
         torch.cuda.synchronize()
         assert int(fe.status.item()) == 0
@@ -103,10 +104,11 @@ def test_maximum_side(fe_mod, pattern, W, H):
 
 @pytest.mark.parametrize("W,H", [(97, 61), (640, 17), (1241, 376)])
 def test_overlapped_path_sizes(fe_mod, pattern, W, H):
-    """The default run (level-0 detection on a second stream beside the
-    pyramid build) against the oracle, down to levels with no cell."""
+    """The overlapped run (level-0 detection on a second stream beside the
+    pyramid build, the default for large batches) against the oracle, down
+    to levels with no cell."""
     l, r = scenes.stereo_pair(90 + W, W, H, 40, 12)
-    run_and_compare(fe_mod, [l, r], Params(), pattern, full_stages=False)
+    run_and_compare(fe_mod, [l, r], Params(), pattern, full_stages=False, overlap=True)
 
 
 def test_flat_images_no_keypoints(fe_mod, pattern):
@@ -170,17 +172,18 @@ def test_deterministic_repeats(fe_mod, pattern):
         fe.close()
 
 
-def test_graph_replay_matches_eager(fe_mod, pattern):
+@pytest.mark.parametrize("overlap", [False, True])
+def test_graph_replay_matches_eager(fe_mod, pattern, overlap):
     import torch
     w = configs.cfg2()
     imgs = w.images()
     fe = fe_mod.Frontend(w.params, [(1241, 376)] * 2, pattern)
     try:
         fe.upload(imgs)
-        fe.run()
+        fe.run(overlap=overlap)
         torch.cuda.synchronize()
         eager = (fe.results(0), fe.results(1), fe.matches(0))
-        fe.capture()
+        fe.capture(overlap=overlap)
         for rep in range(3):
             fe.kp_count.zero_()
             fe.desc.zero_()
