@@ -370,7 +370,7 @@ int32_t vsfe_ctx_destroy(vsfe_ctx *ctx) {
 
 int32_t vsfe_ctx_set_tile(vsfe_ctx *ctx, int32_t tile_w, int32_t tile_h) {
     if (!ctx) return fail(VSFE_EINVAL, "null context");
-    if (tile_w < 8 || tile_w > 128 || tile_h < 8 || tile_h > 32) return fail(VSFE_EINVAL, "tile out of range");
+    if (tile_w < 8 || tile_w > 128 || tile_h < 8 || tile_h > DET_MAX_TILE_H) return fail(VSFE_EINVAL, "tile out of range");
     ctx->tile_w = tile_w;
     ctx->tile_h = tile_h;
     return VSFE_OK;

@@ -48,9 +48,9 @@ constexpr int FT_CHUNKS = 6;                     // 16-byte source chunks per ro
 // padded to 100 so that successive rows start 4 banks apart (fewer bank
 // conflicts when a wave's candidates sit in the same columns of different rows)
 constexpr int FT_W = 100;
-constexpr int FT_MAX_ROWS = 32;
+constexpr int FT_MAX_ROWS = DET_MAX_TILE_H;
 constexpr int FT_ROWS = FT_MAX_ROWS + 6;
-constexpr int FT_MAX_CELLS = 128;               // at most 32 x 4 cells per tile
+constexpr int FT_MAX_CELLS = 32 * DET_MAX_CELLS_Y; // at most 32 x DET_WAVES cells per tile
 constexpr int FT_QW = 448;                                // one wave's candidate queue (more: in rounds)
 
 struct DetParams {
@@ -198,7 +198,7 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 __device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 template <int PF, bool LO, bool P9>
-__global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restrict__ imgs,
+__global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(const ImageDev *__restrict__ imgs,
                                                       const DetItem *__restrict__ items,
                                                       const uint8_t *__restrict__ images,
                                                       const uint8_t *__restrict__ pyr,
@@ -206,10 +206,10 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
                                                       uint32_t *__restrict__ cell_keys,
                                                       uint16_t *__restrict__ crf, DetParams prm) {
     __shared__ __attribute__((aligned(16))) uint32_t tile[FT_ROWS * FT_W];
-    __shared__ uint16_t s_q[4][FT_QW];
+    __shared__ uint16_t s_q[DET_WAVES][FT_QW];
     __shared__ uint32_t s_hi[FT_MAX_CELLS], s_lo[FT_MAX_CELLS];
     __shared__ uint8_t s_run[FT_MAX_CELLS];
-    __shared__ int s_anyw[4];
+    __shared__ int s_anyw[DET_WAVES];
 
     // level-major items in dispatch order, in groups of 16 neighbouring
     // tiles per XCD (shared halo lines hit in that XCD's L2; a contiguous
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
     // (one memory round trip)
     uint32_t mf0 = 1u, mf1 = 1u;
     if (mask) {
-        const int k0 = tid, k1 = tid + 256;
+        const int k0 = tid, k1 = tid + DET_THREADS;
         mf0 = k0 < nk ? mask[lv.cell_offset + (int64_t)(it.cy0 + k0 / it.nkx) * lv.ncx + (it.cx0 + k0 % it.nkx)] : 0u;
         mf1 = k1 < nk ? mask[lv.cell_offset + (int64_t)(it.cy0 + k1 / it.nkx) * lv.ncx + (it.cx0 + k1 % it.nkx)] : 0u;
     }
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
     int my_any = 0;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        const int k = tid + 256 * h;
+        const int k = tid + DET_THREADS * h;
         if (k < nk) {
             const bool run = (h ? mf1 : mf0) != 0u;
             s_run[k] = run;
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
         if (lane == 0) s_anyw[wave] = wave_any;
         __syncthreads();
         if (!(s_anyw[0] | s_anyw[1] | s_anyw[2] | s_anyw[3]) && !crf) {
-            for (int k = tid; k < nk; k += 256)
+            for (int k = tid; k < nk; k += DET_THREADS)
                 cell_keys[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] = 0;
             return;
         }
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
     const int kxl = lane / c, kxh = (FT_HALF + lane) / c;
     uint32_t cm = 0;
 #pragma unroll
-    for (int k = 0; k < FT_MAX_ROWS / 4; k++) {
-        const int r = wv + 4 * k;
+    for (int k = 0; k < FT_MAX_ROWS / DET_WAVES; k++) {
+        const int r = wv + DET_WAVES * k;
         if (r < ylo || r >= yhi) continue;        // uniform
         const uint32_t *t = &tile[(r + 3) * FT_W + lane + 3 + delta];
         uint32_t cand = 0xFFFFFFFFu;
@@ -338,8 +338,8 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
             gm = (s_run[ka] ? 0xFFu : 0u) | (s_run[kb] ? 0xFF0000u : 0u);
         } else {
 #pragma unroll
-            for (int k = 0; k < FT_MAX_ROWS / 4; k++) {
-                const int r = wv + 4 * k;
+            for (int k = 0; k < FT_MAX_ROWS / DET_WAVES; k++) {
+                const int r = wv + DET_WAVES * k;
                 if (r >= th) break;                      // uniform
                 const int kr = (r / c) * it.nkx;
                 gm |= (s_run[kr + ka] ? 1u : 0u) << k;
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
             const int bit = __builtin_ctz(mm);
             mm &= mm - 1;
             if (pos >= r0 && pos < r0 + FT_QW)
-                q[pos - r0] = (uint16_t)(((wv + 4 * (bit & 15)) << 7) | (lane + FT_HALF * (bit >> 4)));
+                q[pos - r0] = (uint16_t)(((wv + DET_WAVES * (bit & 15)) << 7) | (lane + FT_HALF * (bit >> 4)));
             pos++;
         }
     }
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
     const int qr = min(FT_QW, qn - r0);
     // 3b. screen every candidate densely: a run >= p_min at the weaker
     //     threshold is necessary for a corner at either threshold.  Survivors
-    //     (entry = cmin << 14 | rd << 13 | rb << 12 | row << 7 | column) go to
+    //     (entry = cmin << 15 | rd << 14 | rb << 13 | row << 7 | column) go to
     //     a second queue.
     // survivors are compacted in place: after the iteration that reads
     // entries [base, base + 64), at most base + 64 survivors exist, so a
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
         const uint64_t bal = __ballot(surv);
         const int pos2 = n2 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
         if (surv) {
-            q2[pos2] = (uint16_t)((cmin ? 1 << 14 : 0) | (rd ? 1 << 13 : 0) | (rb ? 1 << 12 : 0) | (r << 7) | col);
+            q2[pos2] = (uint16_t)((cmin ? 1 << 15 : 0) | (rd ? 1 << 14 : 0) | (rb ? 1 << 13 : 0) | (r << 7) | col);
         }
         n2 += __popcll(bal);
     }
@@ -479,12 +479,12 @@ __global__ __launch_bounds__(256, 8) void fast_br_kernel(const ImageDev *__restr
     const int ns = n2;
     for (int i = lane; i < ns; i += 64) {
         const int e = q2[i];
-        finish((e >> 7) & 31, e & 127, (e >> 12) & 1, (e >> 13) & 1, (e >> 14) & 1);
+        finish((e >> 7) & 63, e & 127, (e >> 13) & 1, (e >> 14) & 1, (e >> 15) & 1);
     }
     wave_lds_fence();
     }  // rounds
     __syncthreads();
-    for (int k = tid; k < nk; k += 256) {
+    for (int k = tid; k < nk; k += DET_THREADS) {
         const uint32_t hi = s_hi[k], lo = s_lo[k];
         const uint32_t v = hi ? hi : (lo ? (lo | VSFE_KEY_FALLBACK) : 0u);
         cell_keys[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] = v;
@@ -502,10 +502,10 @@ static void launch_fast(const vsfe_batch *b, const DetItem *items, int32_t n_ite
                         const uint8_t *images, const uint8_t *pyr, const uint8_t *mask, uint32_t *keys,
                         uint16_t *crf, const DetParams &prm) {
     if (prm.p_min == 9 && prm.p_max == 13)
-        hipLaunchKernelGGL((fast_br_kernel<PF, LO, true>), dim3(n_items), dim3(256), 0, st, b->d_images, items,
+        hipLaunchKernelGGL((fast_br_kernel<PF, LO, true>), dim3(n_items), dim3(DET_THREADS), 0, st, b->d_images, items,
                            images, pyr, mask, keys, crf, prm);
     else
-        hipLaunchKernelGGL((fast_br_kernel<PF, LO, false>), dim3(n_items), dim3(256), 0, st, b->d_images, items,
+        hipLaunchKernelGGL((fast_br_kernel<PF, LO, false>), dim3(n_items), dim3(DET_THREADS), 0, st, b->d_images, items,
                            images, pyr, mask, keys, crf, prm);
 }
 

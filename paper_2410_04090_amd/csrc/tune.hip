@@ -18,7 +18,7 @@ namespace vsfe {
 
 static void cells_per_tile(int tile_w, int tile_h, int cell, int *nkx, int *nky) {
     *nkx = std::min(32, std::max(1, tile_w / cell));
-    *nky = std::min(4, std::max(1, tile_h / cell));     // at most 32 x 4 cells (detector LDS)
+    *nky = std::min(DET_MAX_CELLS_Y, std::max(1, tile_h / cell));   // at most 32 x DET_WAVES cells (detector LDS)
 }
 
 void det_items_level(const vsfe_batch *b, int level, int tile_w, int tile_h, std::vector<DetItem> *out) {
@@ -47,7 +47,7 @@ void det_items_build(vsfe_batch *b) {
     b->info.n_det_items = b->n_det_items;
 }
 
-static bool tile_ok(int tw, int th) { return tw >= 8 && tw <= 128 && th >= 8 && th <= 32; }
+static bool tile_ok(int tw, int th) { return tw >= 8 && tw <= 128 && th >= 8 && th <= DET_MAX_TILE_H; }
 
 static int32_t upload_items(const std::vector<DetItem> &v, DetItem **dst) {
     *dst = nullptr;
@@ -109,7 +109,7 @@ int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *i
     memset(out, 0, sizeof(*out));
     out->n_levels = L;
     static const int kW[] = {16, 24, 32, 40, 48, 64, 80, 96, 112, 128};
-    static const int kH[] = {8, 12, 16, 24, 32};
+    static const int kH[] = {8, 12, 16, 24, 32, 48, 64};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(VSFE_EHIP, "hipEventCreate failed");
@@ -126,6 +126,7 @@ int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *i
         seen.push_back({nx0, ny0});
         for (int tw : kW)
             for (int th : kH) {
+                if (th > DET_MAX_TILE_H) continue;
                 int nx, ny;
                 cells_per_tile(tw, th, c, &nx, &ny);
                 if (std::find(seen.begin(), seen.end(), std::make_pair(nx, ny)) != seen.end()) continue;
@@ -173,7 +174,7 @@ int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *i
         // store the extent actually used (whole cells) so that every image of
         // the batch gets the same cell counts
         b->tile_w[l] = std::min(128, std::max(8, nx * c));
-        b->tile_h[l] = std::min(32, std::max(8, ny * c));
+        b->tile_h[l] = std::min(DET_MAX_TILE_H, std::max(8, ny * c));
         out->tile_w[l] = nx * c;
         out->tile_h[l] = ny * c;
         out->us[l] = best;

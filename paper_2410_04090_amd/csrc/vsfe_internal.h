@@ -44,6 +44,16 @@ struct PyrItem {
     uint16_t xs, ys, ncols, nrows;
 };
 
+// Detector block: DET_WAVES waves of 64 lanes; a tile is at most 128 pixels
+// wide and 8 rows per wave high, at most 32 x DET_WAVES cells.
+#ifndef VSFE_DET_WAVES
+#define VSFE_DET_WAVES 4
+#endif
+constexpr int DET_WAVES = VSFE_DET_WAVES;
+constexpr int DET_THREADS = 64 * DET_WAVES;
+constexpr int DET_MAX_TILE_H = 8 * DET_WAVES;
+constexpr int DET_MAX_CELLS_Y = DET_WAVES;
+
 // Detector work item: a rectangle of whole cells of one level.
 struct DetItem {
     uint16_t image, level, cx0, cy0, nkx, nky, pad0, pad1;
