@@ -298,20 +298,27 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     const bool okl = lane < tw && gxl >= B && gxl < lv.w - B;
     const bool okh = FT_HALF + lane < tw && gxh >= B && gxh < lv.w - B;
     const us2 e2 = {(unsigned short)prm.eps_min, (unsigned short)prm.eps_min};
-    const us2 one2 = {1, 1};
     const int ylo = max(B - y0, 0), yhi = min(lv.h - B - y0, th);
     const int kxl = lane / c, kxh = (FT_HALF + lane) / c;
     uint32_t cm = 0;
+    // one base address for all rows of the wave: each row then reads at
+    // constant offsets
+    const uint32_t *const t0 = &tile[(wv + 3) * FT_W + lane + 3 + delta];
+    // the west and east neighbours through base registers of their own: the
+    // compiler would otherwise pair one of them with the centre into a
+    // ds_read2, whose short offset field costs an address add per row
+    int w0 = (wv + 3) * FT_W + lane + delta, e0 = w0 + 6;
+    asm volatile("" : "+v"(w0), "+v"(e0));
 #pragma unroll
     for (int k = 0; k < FT_MAX_ROWS / DET_WAVES; k++) {
         const int r = wv + DET_WAVES * k;
         if (r < ylo || r >= yhi) continue;        // uniform
-        const uint32_t *t = &tile[(r + 3) * FT_W + lane + 3 + delta];
-        uint32_t cand = 0xFFFFFFFFu;
+        const uint32_t *t = t0 + DET_WAVES * FT_W * k;
+        uint32_t f = 0x10001u;                    // (low, high) candidate flags
         if (PF) {
             const us2 C = as_us2(t[0]);
             const us2 P0 = as_us2(t[-3 * FT_W]), P8 = as_us2(t[3 * FT_W]);
-            const us2 P4 = as_us2(t[3]), P12 = as_us2(t[-3]);
+            const us2 P4 = as_us2(tile[e0 + DET_WAVES * FT_W * k]), P12 = as_us2(tile[w0 + DET_WAVES * FT_W * k]);
             us2 Mb, Md;
             if (PF == 2) {
                 Mb = __builtin_elementwise_min(__builtin_elementwise_max(P0, P8), __builtin_elementwise_max(P4, P12));
@@ -320,13 +327,16 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
                 Mb = __builtin_elementwise_max(__builtin_elementwise_max(P0, P8), __builtin_elementwise_max(P4, P12));
                 Md = __builtin_elementwise_min(__builtin_elementwise_min(P0, P8), __builtin_elementwise_min(P4, P12));
             }
-            cand = as_u32(__builtin_elementwise_sub_sat(Mb, C + e2)) |
-                   as_u32(__builtin_elementwise_sub_sat(__builtin_elementwise_sub_sat(C, e2), Md));
+            // Mb > C + eps or Md < C - eps, i.e. max(Mb - C, C - Md) > eps
+            // with both differences clamped at zero
+            const us2 d = __builtin_elementwise_max(__builtin_elementwise_sub_sat(Mb, C),
+                                                    __builtin_elementwise_sub_sat(C, Md));
+            // (low != 0, high != 0) of d - eps as two 16-bit flags in one
+            // v_pk_min_u16 (in asm: the compiler would otherwise expand it
+            // into compares and selects)
+            const uint32_t x = as_u32(__builtin_elementwise_sub_sat(d, e2));
+            asm volatile("v_pk_min_u16 %0, %1, %2" : "=v"(f) : "v"(x), "s"(0x10001u));
         }
-        // (low != 0, high != 0) as two 16-bit flags in one v_pk_min_u16 (in asm:
-        // the compiler would otherwise expand it into compares and selects)
-        uint32_t f;
-        asm volatile("v_pk_min_u16 %0, %1, %2" : "=v"(f) : "v"(cand), "v"(as_u32(one2)));
         cm |= f << k;
     }
     cm &= (okl ? 0xFFu : 0u) | (okh ? 0xFF0000u : 0u);
