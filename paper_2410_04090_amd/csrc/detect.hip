@@ -215,8 +215,7 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     // tiles per XCD (shared halo lines hit in that XCD's L2; a contiguous
     // range per XCD would give some XCDs only the heavy level 0)
     const DetItem it = items[xcd_group_item<16>(blockIdx.x, gridDim.x)];
-    const ImageDev &im = imgs[it.image];
-    const LevelDev lv = im.lv[it.level];
+    const DetItem &lv = it;                      // the level's geometry travels with the item
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int c = lv.cell;

@@ -28,9 +28,9 @@ void det_items_level(const vsfe_batch *b, int level, int tile_w, int tile_h, std
         cells_per_tile(tile_w, tile_h, lv.cell, &nkx, &nky);
         for (int cy = 0; cy < lv.ncy; cy += nky)
             for (int cx = 0; cx < lv.ncx; cx += nkx)
-                out->push_back(DetItem{(uint16_t)i, (uint16_t)level, (uint16_t)cx, (uint16_t)cy,
-                                       (uint16_t)std::min(nkx, lv.ncx - cx), (uint16_t)std::min(nky, lv.ncy - cy),
-                                       0, 0});
+                out->push_back(DetItem{level, cx, cy, std::min(nkx, lv.ncx - cx), std::min(nky, lv.ncy - cy),
+                                       lv.w, lv.h, lv.pitch, lv.cell, lv.ncx, lv.offset, lv.cell_offset,
+                                       lv.crf_offset});
     }
 }
 

@@ -54,10 +54,15 @@ constexpr int DET_THREADS = 64 * DET_WAVES;
 constexpr int DET_MAX_TILE_H = 8 * DET_WAVES;
 constexpr int DET_MAX_CELLS_Y = DET_WAVES;
 
-// Detector work item: a rectangle of whole cells of one level.
+// Detector work item: a rectangle of whole cells of one level, with the
+// level's geometry copied in (one 64-byte scalar load per block, no
+// dependent load of the level record).
 struct DetItem {
-    uint16_t image, level, cx0, cy0, nkx, nky, pad0, pad1;
+    int32_t level, cx0, cy0, nkx, nky;           // 32-bit fields: scalar loads only
+    int32_t w, h, pitch, cell, ncx;
+    int64_t offset, cell_offset, crf_offset;
 };
+static_assert(sizeof(DetItem) == 64, "DetItem layout");
 
 // Aggregation work item: PYCA_CHUNK consecutive cells of one level.
 constexpr int PYCA_CHUNK = 256;
