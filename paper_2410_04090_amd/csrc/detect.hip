@@ -377,9 +377,8 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     // with p_min = 9 the screen, which runs at eps_min (eps_lo if there is a
     // fallback threshold, else eps_hi), has already taken the corner decision
     // at that threshold (cmin)
-    auto finish = [&](int r, int col, bool rb, bool rd, bool cmin) {
-        int p[16];
-        const int ctr = load_ring(r, col, p);
+    const uint32_t inv_c = (65535u + (uint32_t)c) / (uint32_t)c;     // ceil(2^16 / c)
+    auto decide = [&](const int *p, int ctr, int r, int col, bool rb, bool rd, bool cmin) {
         bool c_hi = false, c_lo = false;
         if constexpr (P9) {
             // p_min = 9: a bright and a dark run cannot coexist, one polarity decides
@@ -405,7 +404,8 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
         for (int j = 0; j < 16; j += 2)
             score = __builtin_amdgcn_sad_u16((uint32_t)p[j] | ((uint32_t)p[j + 1] << 16), c2, score);
         if (crf && c_hi) crf[lv.crf_offset + (int64_t)(y0 + r) * lv.w + (x0 + col)] = (uint16_t)score;
-        const int kx = col / c, ky = r / c;
+        // col < 128 and r < 32: (v * ceil(2^16 / c)) >> 16 is v / c exactly
+        const int kx = (int)(__umul24((uint32_t)col, inv_c) >> 16), ky = (int)(__umul24((uint32_t)r, inv_c) >> 16);
         const int k = ky * it.nkx + kx;
         if (s_run[k]) {
             const uint32_t off = (uint32_t)((r - ky * c) * c + (col - kx * c));
@@ -413,6 +413,11 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
             if (c_hi) atomicMax(&s_hi[k], key);
             if (c_lo) atomicMax(&s_lo[k], key);
         }
+    };
+    auto finish = [&](int r, int col, bool rb, bool rd, bool cmin) {
+        int p[16];
+        const int ctr = load_ring(r, col, p);
+        decide(p, ctr, r, col, rb, rd, cmin);
     };
 
     // The queue holds FT_QW entries; a wave with more candidates (dense
