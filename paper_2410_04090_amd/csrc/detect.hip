@@ -463,8 +463,10 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
         }
         bool rb = false, rd = false, cmin = false;
         if constexpr (P9) {
-            // one polarity per lane (bright if it passed, else dark), so the
-            // wave does not run both; the other one only if both passed (rare)
+            // one polarity per lane (bright if it passed, else dark); the
+            // other one only if both passed and the first has no run (a sixth
+            // or more of the candidates, so nearly every wave runs it; moving
+            // those to the decision pass measured no faster)
             bool dk = !pb;
             uint32_t m = ring_mask(p, ctr, prm.eps_min, dk);
             bool run = run_ge<true>(m, 9);
