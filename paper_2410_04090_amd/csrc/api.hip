@@ -273,7 +273,8 @@ int32_t vsfe_params_check(const vsfe_params *p) {
         return fail(VSFE_EINVAL, "need 1 <= p_min <= p_max <= 16");
     if (p->border < 3 || p->border > 64) return fail(VSFE_EINVAL, "border out of 3..64");
     if (p->n_levels < 1 || p->n_levels > VSFE_MAX_LEVELS) return fail(VSFE_EINVAL, "n_levels out of range");
-    if (p->cell0 < 8 || p->cell0 > 32) return fail(VSFE_EINVAL, "cell0 out of 8..32");
+    // a detector tile holds at least one whole cell (DET_MAX_TILE_H = 32 rows)
+    if (p->cell0 < 8 || p->cell0 > DET_MAX_TILE_H) return fail(VSFE_EINVAL, "cell0 out of 8..32");
     if (cell_size(p->cell0, p->n_levels - 1) < 1) return fail(VSFE_EINVAL, "cell side vanishes at the last level");
     if (p->pfa != 0 && p->pfa != 1) return fail(VSFE_EINVAL, "pfa must be 0 or 1");
     if (p->nms_mode != 0 && p->nms_mode != 1) return fail(VSFE_EINVAL, "nms_mode must be 0 or 1");
@@ -320,7 +321,7 @@ int32_t vsfe_ctx_create(const vsfe_params *p, const int8_t *pattern, vsfe_ctx **
     c->p = *p;
     c->device = dev;
     c->tile_w = 128;
-    c->tile_h = 32;
+    c->tile_h = DET_MAX_TILE_H;
     for (int l = 0; l < VSFE_MAX_LEVELS; l++) {
         c->scale_q16[l] = scale_q16(l);
         c->cell[l] = cell_size(p->cell0, l);

@@ -277,7 +277,10 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
         const bool wave_any = __ballot(my_any) != 0;
         if (lane == 0) s_anyw[wave] = wave_any;
         __syncthreads();
-        if (!(s_anyw[0] | s_anyw[1] | s_anyw[2] | s_anyw[3]) && !crf) {
+        int any = 0;
+#pragma unroll
+        for (int w = 0; w < DET_WAVES; w++) any |= s_anyw[w];
+        if (!any && !crf) {
             for (int k = tid; k < nk; k += DET_THREADS)
                 cell_keys[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] = 0;
             return;
