@@ -116,7 +116,10 @@ __device__ __forceinline__ uint32_t pack_byte1(const i32x4 &a) {
 // tables are read once, and the current keypoint's pattern is read before
 // the next prefetch is issued, so no wait inside the loop waits for the
 // prefetch.  Slot state is wave-uniform (scalar registers).
-__global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ imgs, const uint8_t *__restrict__ images,
+// At most 80 VGPRs, six waves per SIMD (the LDS of six blocks fits): the
+// only spills are on the clamped-border staging path and the unsmoothed
+// path; seven waves (72 VGPRs) spill in the loop and run slower.
+__global__ __launch_bounds__(256, 6) void orb_kernel(const ImageDev *__restrict__ imgs, const uint8_t *__restrict__ images,
                                                   const uint8_t *__restrict__ pyr, vsfe_kp_soa kps,
                                                   const int32_t *__restrict__ kp_count,
                                                   const uint32_t *__restrict__ pat_off, uint32_t *__restrict__ desc,
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
     }
     __syncthreads();
     const long band = (long)c_smooth.band[lane];
-    int64_t bx = 0, by = 0;
+    int bx = 0, by = 0;                          // Q14 boundary directions (32-bit: fewer registers)
     if (lane < 30) {
         bx = a.tab.bin_x[lane];
         by = a.tab.bin_y[lane];
@@ -152,9 +155,11 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
     // staging tasks of this lane: dword t = lane + 64 u is row t / 10, word t % 10
     // (its LDS word is t itself: rows are 10 words apart)
     static_assert(R_STRIDE == 40, "staging assumes 10 words per row");
-    int t_row[6];
+    // (rows < 64: one byte each, two registers instead of six)
+    uint32_t t_rows[2] = {0u, 0u};
 #pragma unroll
-    for (int u = 0; u < 6; u++) t_row[u] = (lane + 64 * u) / 10;
+    for (int u = 0; u < 6; u++) t_rows[u >> 2] |= (uint32_t)((lane + 64 * u) / 10) << (8 * (u & 3));
+    auto t_row = [&](int u) { return (int)((t_rows[u >> 2] >> (8 * (u & 3))) & 0xFFu); };
 
     // Keypoint metadata of the wave's next 64 iterations, one iteration per
     // lane (slot, counts, coordinates, level geometry: three dependent
@@ -205,14 +210,14 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
             const uint8_t *base = src + (int64_t)(y - 18) * pitch + xs;
 #pragma unroll
             for (int u = 0; u < 6; u++)
-                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const uint32_t *)(base + t_row[u] * (pitch - 40) + 4 * (lane + 64 * u)) : 0u;
+                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const uint32_t *)(base + t_row(u) * (pitch - 40) + 4 * (lane + 64 * u)) : 0u;
         } else {
 #pragma unroll
             for (int u = 0; u < 6; u++) {
                 p_v[u] = 0u;
                 if (lane + 64 * u < 37 * 10) {
-                    const int gy = min(max(y - 18 + t_row[u], 0), lh - 1);
-                    p_v[u] = fetch4c(src + (int64_t)gy * pitch, xs + 4 * (lane + 64 * u - 10 * t_row[u]), lw);
+                    const int gy = min(max(y - 18 + t_row(u), 0), lh - 1);
+                    p_v[u] = fetch4c(src + (int64_t)gy * pitch, xs + 4 * (lane + 64 * u - 10 * t_row(u)), lw);
                 }
             }
         }
@@ -255,7 +260,7 @@ __global__ __launch_bounds__(256) void orb_kernel(const ImageDev *__restrict__ i
         bool ge = false;
         if (lane < 30) {
             const int hm = half_plane(m10, m01), hb = half_plane(bx, by);
-            ge = hm != hb ? hm > hb : (bx * (int64_t)m01 - by * (int64_t)m10 >= 0);
+            ge = hm != hb ? hm > hb : ((int64_t)bx * m01 - (int64_t)by * m10 >= 0);
         }
         const uint64_t gem = __ballot(ge);
         const int bin = (m10 == 0 && m01 == 0) ? 0 : (__popcll(gem) % 30);
