@@ -200,9 +200,8 @@ static int32_t plan_batch(const vsfe_params &p, int tile_w, int tile_h, int32_t 
                     const int ncols = ((xa1 - xa0 + 1) + 15) & ~15, nrows = ya1 - ya0 + 1;
                     if (ncols > PYR_SW || nrows > PYR_SH)
                         return fail(VSFE_ECAPACITY, "pyramid source window exceeds the staging buffer");
-                    (void)s;
-                    b->h_pyr_items.push_back(PyrItem{(uint16_t)i, (uint16_t)tx, (uint16_t)ty, 0, (uint16_t)xa0,
-                                                     (uint16_t)ya0, (uint16_t)ncols, (uint16_t)nrows});
+                    b->h_pyr_items.push_back(PyrItem{s.offset, lv.offset, s.w, s.h, s.pitch, lv.w, lv.h, lv.pitch,
+                                                     lv.xtab, lv.ytab, tx, ty, xa0, ya0, ncols, nrows});
                 }
         }
     }

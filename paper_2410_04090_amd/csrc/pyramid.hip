@@ -41,8 +41,9 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
                                                             uint8_t *__restrict__ pyr, int aligned0) {
     __shared__ __attribute__((aligned(16))) uint32_t s_src[PYR_SH * (PYR_LDS_W / 4)];
     const PyrItem it = items[xcd_item(blockIdx.x, gridDim.x)];
-    const LevelDev s = imgs[it.image].lv[level - 1];
-    const LevelDev d = imgs[it.image].lv[level];
+    const struct { int w, h, pitch; int64_t offset; } s = {it.sw, it.sh, it.spitch, it.src_offset};
+    const struct { int w, h, pitch, xtab, ytab; int64_t offset; } d = {it.dw, it.dh, it.dpitch, it.xtab, it.ytab,
+                                                                      it.dst_offset};
     const uint8_t *src = (level == 1 ? images : pyr) + s.offset;
     uint8_t *dst = pyr + d.offset;
     const int tid = threadIdx.x;
@@ -72,9 +73,9 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
         const int q = tid + 256 * u;
         const int rr = q / CPR, k = q - rr * CPR;
         at[u] = -1;
-        if (rr < (int)it.nrows && 16 * k < (int)it.ncols) {
-            const int gy = min((int)it.ys + rr, s.h - 1);
-            v[u] = fetch16c(src + (int64_t)gy * s.pitch, (int)it.xs + 16 * k, s.w, aligned);
+        if (rr < it.nrows && 16 * k < it.ncols) {
+            const int gy = min(it.ys + rr, s.h - 1);
+            v[u] = fetch16c(src + (int64_t)gy * s.pitch, it.xs + 16 * k, s.w, aligned);
             at[u] = rr * (PYR_LDS_W / 16) + k;
         }
     }
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
     int o[4], fx[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-        o[j] = (int)(ex[j] & 0xFFFFu) - (int)it.xs;
+        o[j] = (int)(ex[j] & 0xFFFFu) - it.xs;
         fx[j] = (int)(ex[j] >> 16);
     }
     // byte selectors of (a0, a1), (b0, b1), (a2, a3), (b2, b3) within the
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
         const int oy = oy0 + k;
         if (oy >= d.h) break;                            // uniform
         const uint32_t e = ey[k];
-        const int ya = (int)(e & 0xFFFFu) - (int)it.ys;
+        const int ya = (int)(e & 0xFFFFu) - it.ys;
         const uint32_t fy = e >> 16, wy = 256u - fy;
         if (ya == cur + 1) {                             // slide by one row
             t01 = u01;

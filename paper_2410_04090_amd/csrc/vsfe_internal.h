@@ -39,10 +39,16 @@ constexpr int PYR_TW = 256;   // 64 lanes x 4 columns
 constexpr int PYR_TH = 32;    // 4 waves x 8 rows
 constexpr int PYR_SW = 336;
 constexpr int PYR_SH = 44;
+// One output tile of one level with both levels' geometry copied in (32-bit
+// fields: the block reads its item with scalar loads, no dependent load of
+// the level records).
 struct PyrItem {
-    uint16_t image, tx, ty, pad;
-    uint16_t xs, ys, ncols, nrows;
+    int64_t src_offset, dst_offset;           // level l-1 / level l in their buffers
+    int32_t sw, sh, spitch, dw, dh, dpitch;   // source and output level sizes and pitches
+    int32_t xtab, ytab;                       // output level's resampling table entries
+    int32_t tx, ty, xs, ys, ncols, nrows;     // tile, staged source window
 };
+static_assert(sizeof(PyrItem) == 72, "PyrItem layout");
 
 // Detector block: DET_WAVES waves of 64 lanes; a tile is at most 128 pixels
 // wide and 8 rows per wave high, at most 32 x DET_WAVES cells.
