@@ -17,6 +17,8 @@
 //   the first (in canonical order) cells with rank == T are kept; a block
 //   prefix sum compacts the survivors into the keypoint arrays in canonical
 //   order (level, cell row, cell column).
+#include <string.h>
+
 #include "vsfe_internal.h"
 
 namespace vsfe {
@@ -41,23 +43,27 @@ __device__ __forceinline__ int project_q16(int x, int S, int limit) {
 // floor(x / c) = (x * (floor(2^20 / c) + 1)) >> 20, exact for 0 <= x < 8192
 // (the largest image side) and c <= 128 (the error, below x / 2^20 < 1/128,
 // stays under 1 / c); cells are at most 32 pixels.
+// Per-level constants of the aggregation, the same for every image of a
+// batch (level scale and cell side come from the parameters): 1 / scale
+// and ceil(2^20 / cell), the multiplier that divides offsets below 1024 by
+// the cell side exactly.
+struct PfaLevelTab {
+    float inv[VSFE_MAX_LEVELS];
+    uint32_t mag[VSFE_MAX_LEVELS];
+};
+
 template <int R, bool FIX2>
 __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restrict__ imgs,
                                                        const CellChunk *__restrict__ chunks,
                                                        const uint32_t *__restrict__ cell_keys,
-                                                       uint32_t *__restrict__ rank, int pfa, int nms_mode) {
+                                                       uint32_t *__restrict__ rank, int pfa, int nms_mode,
+                                                       PfaLevelTab tab) {
     constexpr int Q = 2 * R + 1, NS = Q * Q, CENTER = R * Q + R;
-    __shared__ float s_inv[VSFE_MAX_LEVELS];
-    __shared__ uint32_t s_mag[VSFE_MAX_LEVELS];
     __shared__ uint32_t s_acc[NS][256];     // each thread's window sums (thread-private columns)
+    const float *s_inv = tab.inv;           // per level, the same for every image of the batch
+    const uint32_t *s_mag = tab.mag;
     const CellChunk ch = chunks[xcd_item(blockIdx.x, gridDim.x)];
     const ImageDev &im = imgs[ch.image];
-    if (threadIdx.x < (unsigned)im.n_levels) {
-        const LevelDev L = im.lv[threadIdx.x];
-        s_inv[threadIdx.x] = 65536.0f / (float)L.scale_q16;
-        s_mag[threadIdx.x] = (1u << 20) / (uint32_t)L.cell + 1u;
-    }
-    __syncthreads();
     const LevelDev lv = im.lv[ch.level];
     const int idx = (int)ch.first + (int)threadIdx.x;
     if (idx >= lv.ncx * lv.ncy) return;
@@ -369,14 +375,20 @@ extern "C" int32_t pyca_cull_aggregate(const vsfe_ctx *ctx, const vsfe_batch *b,
             const double s_l = ctx->scale_q16[l] / 65536.0;
             if ((2 * p.nms_radius + 1) / s_l + 3.0 > (double)ctx->cell[l]) fix2 = false;
         }
+        PfaLevelTab tab;
+        memset(&tab, 0, sizeof(tab));
+        for (int l = 0; l < p.n_levels; l++) {
+            tab.inv[l] = 65536.0f / (float)ctx->scale_q16[l];
+            tab.mag[l] = (1u << 20) / (uint32_t)ctx->cell[l] + 1u;
+        }
 #define VSFE_PFA_LAUNCH(R_)                                                                                       \
     do {                                                                                                          \
         if (fix2)                                                                                                 \
             hipLaunchKernelGGL((pfa_eval_kernel<R_, true>), dim3(b->n_chunks), dim3(256), 0, st, b->d_images,    \
-                               b->d_chunks, cell_keys, rank, p.pfa, p.nms_mode);                                  \
+                               b->d_chunks, cell_keys, rank, p.pfa, p.nms_mode, tab);                             \
         else                                                                                                      \
             hipLaunchKernelGGL((pfa_eval_kernel<R_, false>), dim3(b->n_chunks), dim3(256), 0, st, b->d_images,   \
-                               b->d_chunks, cell_keys, rank, p.pfa, p.nms_mode);                                  \
+                               b->d_chunks, cell_keys, rank, p.pfa, p.nms_mode, tab);                             \
     } while (0)
         switch (p.nms_radius) {
             case 0: VSFE_PFA_LAUNCH(0); break;
