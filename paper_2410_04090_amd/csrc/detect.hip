@@ -51,7 +51,8 @@ constexpr int FT_W = 100;
 constexpr int FT_MAX_ROWS = DET_MAX_TILE_H;
 constexpr int FT_ROWS = FT_MAX_ROWS + 6;
 constexpr int FT_MAX_CELLS = 32 * DET_MAX_CELLS_Y; // at most 32 x DET_WAVES cells per tile
-constexpr int FT_QW = 448;                                // one wave's candidate queue (more: in rounds)
+constexpr int FT_QW = 384;                                // one wave's candidate queue (more: in rounds)
+constexpr int FT_DQ = 128;                                // one wave's deferred second-polarity list
 
 struct DetParams {
     int eps_hi, eps_lo, p_min, p_max, border, eps_min, aligned;
@@ -207,6 +208,7 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
                                                       uint16_t *__restrict__ crf, DetParams prm) {
     __shared__ __attribute__((aligned(16))) uint32_t tile[FT_ROWS * FT_W];
     __shared__ uint16_t s_q[DET_WAVES][FT_QW];
+    __shared__ uint16_t s_d[DET_WAVES][FT_DQ];
     __shared__ uint32_t s_hi[FT_MAX_CELLS], s_lo[FT_MAX_CELLS];
     __shared__ uint8_t s_run[FT_MAX_CELLS];
     __shared__ int s_anyw[DET_WAVES];
@@ -448,6 +450,30 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     // survivor never overwrites an entry that is still to be read
     uint16_t *const q2 = q;
     int n2 = 0;                                  // survivors so far (uniform)
+    auto emit = [&](bool surv, int entry) {
+        const uint64_t bal = __ballot(surv);
+        const int pos2 = n2 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+        if (surv) q2[pos2] = (uint16_t)entry;
+        n2 += __popcll(bal);
+    };
+    // p_min = 9: a lane tests one polarity (bright if it passed the compass
+    // test, else dark).  A pixel that passed both and has no bright run (a
+    // sixth to a quarter of the candidates, so nearly every batch has one)
+    // is deferred to this wave's list and tested dark in dense batches of
+    // 64; a deferred pixel's survivor is still at most one output per
+    // candidate, so the in-place compaction above stays valid.
+    uint16_t *const dq = s_d[wv];
+    int nd = 0;                                  // deferred entries (uniform)
+    auto screen_dark = [&](int first, int count) {
+        const bool a = lane < count;
+        const int e = a ? dq[first + lane] : 0;
+        int p[16];
+        const int ctr = load_ring((e >> 7) & 63, e & 127, p);
+        const uint32_t m = ring_mask(p, ctr, prm.eps_min, true);
+        const bool run = run_ge<true>(m, 9);
+        const bool cmin = run && !run_ge<false>(m, 14);
+        emit(a && run, (cmin ? 1 << 15 : 0) | (1 << 14) | (e & 0x1FFF));
+    };
     for (int base = 0; base < qr; base += 64) {
         const int i = base + lane;
         const bool act = i < qr;
@@ -464,20 +490,12 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
             pb = max(max(p[0], p[8]), max(p[4], p[12])) > ctr + prm.eps_min;
             pd = min(min(p[0], p[8]), min(p[4], p[12])) < ctr - prm.eps_min;
         }
-        bool rb = false, rd = false, cmin = false;
+        bool rb = false, rd = false, cmin = false, defer = false;
         if constexpr (P9) {
-            // one polarity per lane (bright if it passed, else dark); the
-            // other one only if both passed and the first has no run (a sixth
-            // or more of the candidates, so nearly every wave runs it; moving
-            // those to the decision pass measured no faster)
-            bool dk = !pb;
-            uint32_t m = ring_mask(p, ctr, prm.eps_min, dk);
-            bool run = run_ge<true>(m, 9);
-            if (!run && pb && pd) {
-                dk = true;
-                m = ring_mask(p, ctr, prm.eps_min, true);
-                run = run_ge<true>(m, 9);
-            }
+            const bool dk = !pb;
+            const uint32_t m = ring_mask(p, ctr, prm.eps_min, dk);
+            const bool run = run_ge<true>(m, 9);
+            defer = act && !run && pb && pd;
             rb = run && !dk;
             rd = run && dk;
             cmin = run && !run_ge<false>(m, 14);
@@ -485,13 +503,25 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
             if (pb) rb = run_ge<false>(ring_mask(p, ctr, prm.eps_min, false), prm.p_min);
             if (pd) rd = run_ge<false>(ring_mask(p, ctr, prm.eps_min, true), prm.p_min);
         }
-        const bool surv = act && (rb || rd);
-        const uint64_t bal = __ballot(surv);
-        const int pos2 = n2 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-        if (surv) {
-            q2[pos2] = (uint16_t)((cmin ? 1 << 15 : 0) | (rd ? 1 << 14 : 0) | (rb ? 1 << 13 : 0) | (r << 7) | col);
+        emit(act && (rb || rd), (cmin ? 1 << 15 : 0) | (rd ? 1 << 14 : 0) | (rb ? 1 << 13 : 0) | (r << 7) | col);
+        if constexpr (P9) {
+            const uint64_t bd = __ballot(defer);
+            if (bd) {                                // uniform
+                const int posd = nd + __builtin_amdgcn_mbcnt_hi((uint32_t)(bd >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bd, 0));
+                if (defer) dq[posd] = (uint16_t)(e & 0x1FFF);
+                nd += __popcll(bd);                  // < 64 before, <= 127 after
+                if (nd >= 64) {
+                    nd -= 64;
+                    wave_lds_fence();
+                    screen_dark(nd, 64);
+                }
+            }
         }
-        n2 += __popcll(bal);
+    }
+    if (P9 && nd > 0) {
+        wave_lds_fence();
+        screen_dark(0, nd);
     }
     wave_lds_fence();
     // 3c. decide this wave's survivors densely, then reduce over the block
