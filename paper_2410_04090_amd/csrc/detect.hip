@@ -313,10 +313,12 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     // ds_read2, whose short offset field costs an address add per row
     int w0 = (wv + 3) * FT_W + lane + delta, e0 = w0 + 6;
     asm volatile("" : "+v"(w0), "+v"(e0));
+    // this wave's rows wv + 4k inside [ylo, yhi): k in [k_lo, k_hi)
+    const int k_lo = max(ylo - wv + DET_WAVES - 1, 0) / DET_WAVES;
+    const uint32_t k_n = (uint32_t)max((yhi - wv + DET_WAVES - 1) / DET_WAVES - k_lo, 0);
 #pragma unroll
     for (int k = 0; k < FT_MAX_ROWS / DET_WAVES; k++) {
-        const int r = wv + DET_WAVES * k;
-        if (r < ylo || r >= yhi) continue;        // uniform
+        if ((uint32_t)(k - k_lo) >= k_n) continue;                    // uniform
         const uint32_t *t = t0 + DET_WAVES * FT_W * k;
         uint32_t f = 0x10001u;                    // (low, high) candidate flags
         if (PF) {
