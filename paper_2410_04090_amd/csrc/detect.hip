@@ -198,6 +198,18 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 // operations complete in order; this stops the compiler from moving reads up)
 __device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
+// ceil(2^16 / d) for d = 1..32 (cell sides and cells per tile row): for
+// v < 128, (v * ceil(2^16 / d)) >> 16 = v / d exactly.
+struct InvTable {
+    uint32_t v[33];
+};
+constexpr InvTable make_inv_table() {
+    InvTable t{};
+    for (uint32_t d = 1; d <= 32; d++) t.v[d] = (65535u + d) / d;
+    return t;
+}
+__constant__ InvTable c_inv16 = make_inv_table();
+
 template <int PF, bool LO, bool P9>
 __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(const ImageDev *__restrict__ imgs,
                                                       const DetItem *__restrict__ items,
@@ -303,7 +315,10 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     const bool okh = FT_HALF + lane < tw && gxh >= B && gxh < lv.w - B;
     const us2 e2 = {(unsigned short)prm.eps_min, (unsigned short)prm.eps_min};
     const int ylo = max(B - y0, 0), yhi = min(lv.h - B - y0, th);
-    const int kxl = lane / c, kxh = (FT_HALF + lane) / c;
+    // v < 128: (v * ceil(2^16 / d)) >> 16 is v / d exactly (for d <= 256)
+    const uint32_t inv_c = c_inv16.v[c], inv_nkx = c_inv16.v[it.nkx];   // c, nkx <= 32
+    auto div_c = [&](int v) { return (int)(__umul24((uint32_t)v, inv_c) >> 16); };
+    const int kxl = div_c(lane), kxh = div_c(FT_HALF + lane);
     uint32_t cm = 0;
     // one base address for all rows of the wave: each row then reads at
     // constant offsets
@@ -313,6 +328,10 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     // ds_read2, whose short offset field costs an address add per row
     int w0 = (wv + 3) * FT_W + lane + delta, e0 = w0 + 6;
     asm volatile("" : "+v"(w0), "+v"(e0));
+    // the flag clamp's (1, 1) in a scalar register set once (as a constant
+    // the compiler would write it again for every row)
+    uint32_t one2;
+    asm volatile("s_mov_b32 %0, 0x10001" : "=s"(one2));
     // this wave's rows wv + 4k inside [ylo, yhi): k in [k_lo, k_hi)
     const int k_lo = max(ylo - wv + DET_WAVES - 1, 0) / DET_WAVES;
     const uint32_t k_n = (uint32_t)max((yhi - wv + DET_WAVES - 1) / DET_WAVES - k_lo, 0);
@@ -341,7 +360,7 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
             // v_pk_min_u16 (in asm: the compiler would otherwise expand it
             // into compares and selects)
             const uint32_t x = as_u32(__builtin_elementwise_sub_sat(d, e2));
-            asm volatile("v_pk_min_u16 %0, %1, %2" : "=v"(f) : "v"(x), "s"(0x10001u));
+            asm volatile("v_pk_min_u16 %0, %1, %2" : "=v"(f) : "v"(x), "s"(one2));
         }
         cm |= f << k;
     }
@@ -384,7 +403,6 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     // with p_min = 9 the screen, which runs at eps_min (eps_lo if there is a
     // fallback threshold, else eps_hi), has already taken the corner decision
     // at that threshold (cmin)
-    const uint32_t inv_c = (65535u + (uint32_t)c) / (uint32_t)c;     // ceil(2^16 / c)
     auto decide = [&](const int *p, int ctr, int r, int col, bool rb, bool rd, bool cmin) {
         bool c_hi = false, c_lo = false;
         if constexpr (P9) {
@@ -411,8 +429,7 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
         for (int j = 0; j < 16; j += 2)
             score = __builtin_amdgcn_sad_u16((uint32_t)p[j] | ((uint32_t)p[j + 1] << 16), c2, score);
         if (crf && c_hi) crf[lv.crf_offset + (int64_t)(y0 + r) * lv.w + (x0 + col)] = (uint16_t)score;
-        // col < 128 and r < 32: (v * ceil(2^16 / c)) >> 16 is v / c exactly
-        const int kx = (int)(__umul24((uint32_t)col, inv_c) >> 16), ky = (int)(__umul24((uint32_t)r, inv_c) >> 16);
+        const int kx = div_c(col), ky = div_c(r);                     // col < 128, r < 32
         const int k = ky * it.nkx + kx;
         if (s_run[k]) {
             const uint32_t off = (uint32_t)((r - ky * c) * c + (col - kx * c));
@@ -535,10 +552,11 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     wave_lds_fence();
     }  // rounds
     __syncthreads();
-    for (int k = tid; k < nk; k += DET_THREADS) {
+    for (int k = tid; k < nk; k += DET_THREADS) {       // nk <= 128
         const uint32_t hi = s_hi[k], lo = s_lo[k];
         const uint32_t v = hi ? hi : (lo ? (lo | VSFE_KEY_FALLBACK) : 0u);
-        cell_keys[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] = v;
+        const int ky = (int)(__umul24((uint32_t)k, inv_nkx) >> 16), kx = k - ky * it.nkx;
+        cell_keys[lv.cell_offset + (int64_t)(it.cy0 + ky) * lv.ncx + (it.cx0 + kx)] = v;
     }
 }
 

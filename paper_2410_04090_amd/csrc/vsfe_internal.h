@@ -137,10 +137,13 @@ namespace vsfe {
 // (neighbouring tiles share halo rows and cache lines in one L2).  A
 // bijection on [0, n).
 constexpr int N_XCD = 8;
+// (Unsigned arithmetic: block indices and counts are never negative, and
+// unsigned division by a power of two is a plain shift.)
 __device__ __forceinline__ int xcd_item(int b, int n) {
-    const int q = n / N_XCD, r = n % N_XCD;
-    const int x = b % N_XCD, k = b / N_XCD;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+    const unsigned ub = (unsigned)b, un = (unsigned)n;
+    const unsigned q = un / N_XCD, r = un % N_XCD;
+    const unsigned x = ub % N_XCD, k = ub / N_XCD;
+    return (int)((x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k);
 }
 
 // XCD-aware order that keeps the dispatch order: groups of G consecutive
@@ -151,10 +154,11 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
 // [0, n).
 template <int G>
 __device__ __forceinline__ int xcd_group_item(int b, int n) {
-    const int full = n / (N_XCD * G) * (N_XCD * G);
-    if (b >= full) return b;
-    const int x = b % N_XCD, k = b / N_XCD;
-    return ((k / G) * N_XCD + x) * G + k % G;
+    const unsigned ub = (unsigned)b, un = (unsigned)n;
+    const unsigned full = un / (N_XCD * G) * (N_XCD * G);
+    if (ub >= full) return b;
+    const unsigned x = ub % N_XCD, k = ub / N_XCD;
+    return (int)(((k / G) * N_XCD + x) * G + k % G);
 }
 
 void set_error(const std::string &msg);
