@@ -253,14 +253,26 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
         mf0 = k0 < nk ? mask[lv.cell_offset + (int64_t)(it.cy0 + k0 / it.nkx) * lv.ncx + (it.cx0 + k0 % it.nkx)] : 0u;
         mf1 = k1 < nk ? mask[lv.cell_offset + (int64_t)(it.cy0 + k1 / it.nkx) * lv.ncx + (it.cx0 + k1 % it.nkx)] : 0u;
     }
+    // an interior tile (every staged chunk inside the level, aligned rows)
+    // loads without per-thread checks (uniform)
+    const bool interior = aligned && xb >= 0 && xb + FT_HALF + 16 * FT_CHUNKS <= lv.w && y0 >= 3 &&
+                          y0 + th + 3 <= lv.h;
     if (tid < (th + 6) * FT_CHUNKS) {
         const int rr = tid / FT_CHUNKS, m = tid - rr * FT_CHUNKS;
         const int gy = y0 - 3 + rr;
-        uint4 L = make_uint4(0, 0, 0, 0), R = make_uint4(0, 0, 0, 0);
-        if (gy >= 0 && gy < lv.h) {
-            const uint8_t *row = src + (int64_t)gy * lv.pitch;
-            L = fetch16(row, xb + 16 * m, lv.w, aligned);
-            R = fetch16(row, xb + FT_HALF + 16 * m, lv.w, aligned);
+        uint4 L, R;
+        if (interior) {
+            const uint8_t *row = src + (int64_t)gy * lv.pitch + xb + 16 * m;
+            L = *(const uint4 *)row;
+            R = *(const uint4 *)(row + FT_HALF);
+        } else {
+            L = make_uint4(0, 0, 0, 0);
+            R = make_uint4(0, 0, 0, 0);
+            if (gy >= 0 && gy < lv.h) {
+                const uint8_t *row = src + (int64_t)gy * lv.pitch;
+                L = fetch16(row, xb + 16 * m, lv.w, aligned);
+                R = fetch16(row, xb + FT_HALF + 16 * m, lv.w, aligned);
+            }
         }
         uint4 *dst = (uint4 *)&tile[rr * FT_W + 16 * m];
         const uint32_t l4[4] = {L.x, L.y, L.z, L.w}, r4[4] = {R.x, R.y, R.z, R.w};
