@@ -205,12 +205,18 @@ __global__ __launch_bounds__(256, 6) void orb_kernel(const ImageDev *__restrict_
         const bool aligned = !(fl & 2u) || a.aligned0;
         const int xs = (x - 18) & ~3;
         p_delta = (x - 18) - xs;
-        if (aligned && y >= 18 && y + 18 < lh && xs >= 0 && xs + 40 <= lw) {
+        if (aligned && y >= 18 && y + 18 < lh && xs >= 0 && xs + 40 <= lw && pitch < (1 << 24)) {
             // the whole 40 x 37 window lies inside the level: plain 32-bit loads
+            // (32-bit per-lane offsets from a uniform base: 24-bit
+            // multiply-adds and scalar-base addressing, no 64-bit lane math;
+            // 36 rows of a pitch below 2^24 stay below 2^32)
             const uint8_t *base = src + (int64_t)(y - 18) * pitch + xs;
+            const uint32_t step = (uint32_t)(pitch - 40);
 #pragma unroll
-            for (int u = 0; u < 6; u++)
-                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const uint32_t *)(base + t_row(u) * (pitch - 40) + 4 * (lane + 64 * u)) : 0u;
+            for (int u = 0; u < 6; u++) {
+                const uint32_t off = __umul24((uint32_t)t_row(u), step) + 4u * (uint32_t)(lane + 64 * u);
+                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const uint32_t *)(base + off) : 0u;
+            }
         } else {
 #pragma unroll
             for (int u = 0; u < 6; u++) {
