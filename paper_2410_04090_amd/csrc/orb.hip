@@ -168,8 +168,12 @@ __global__ __launch_bounds__(256, 6) void orb_kernel(const ImageDev *__restrict_
     const int64_t first = (int64_t)xcd_item(blockIdx.x, gridDim.x) * ORB_WAVES + wave;
     const int64_t nw = (int64_t)gridDim.x * ORB_WAVES;
     const int64_t n_slots = (int64_t)a.n_images * a.n_max;
-    uint32_t m_xy = 0, m_wh = 0, m_pitch = 0, m_flags = 0;   // flags: 1 = active, 2 = level 0
-    uint64_t m_off = 0;                                     // level offset in its buffer
+    // flags: 1 = active, 2 = level 0, 4 = interior (the whole 40 x 37 window
+    // inside an aligned level with a pitch below 2^24), bits 8-9 = the
+    // window's byte offset in its first word; m_addr = the window's first
+    // word (interior) or the level's first byte
+    uint32_t m_xy = 0, m_wh = 0, m_pitch = 0, m_flags = 0;
+    uint64_t m_addr = 0;
     auto load_meta = [&](int64_t k0) {
         const int64_t sl = first + (k0 + lane) * nw;
         m_flags = 0;
@@ -181,8 +185,13 @@ __global__ __launch_bounds__(256, 6) void orb_kernel(const ImageDev *__restrict_
                 m_xy = (uint32_t)x | ((uint32_t)y << 16);
                 m_wh = (uint32_t)lv.w | ((uint32_t)lv.h << 16);
                 m_pitch = (uint32_t)lv.pitch;
-                m_off = (uint64_t)lv.offset;
-                m_flags = 1u | (lvl == 0 ? 2u : 0u);
+                const uint8_t *src = (lvl == 0 ? images : pyr) + lv.offset;
+                const int xs = (x - 18) & ~3;
+                const bool aligned = lvl != 0 || a.aligned0;
+                const bool interior = aligned && y >= 18 && y + 18 < lv.h && xs >= 0 && xs + 40 <= lv.w &&
+                                      lv.pitch < (1 << 24);
+                m_addr = (uint64_t)(interior ? src + (int64_t)(y - 18) * lv.pitch + xs : src);
+                m_flags = 1u | (lvl == 0 ? 2u : 0u) | (interior ? 4u : 0u) | ((uint32_t)((x - 18) - xs) << 8);
             }
         }
     };
@@ -195,35 +204,38 @@ __global__ __launch_bounds__(256, 6) void orb_kernel(const ImageDev *__restrict_
         const uint32_t fl = __builtin_amdgcn_readlane(m_flags, j);
         p_act = (fl & 1u) != 0;
         if (!p_act) return;
-        const uint32_t xy = __builtin_amdgcn_readlane(m_xy, j), wh = __builtin_amdgcn_readlane(m_wh, j);
-        const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
-        const int lw = (int)(wh & 0xFFFFu), lh = (int)(wh >> 16);
+        p_delta = (int)((fl >> 8) & 3u);
         const int pitch = (int)__builtin_amdgcn_readlane(m_pitch, j);
-        const int64_t off = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(m_off >> 32), j) << 32) |
-                                      __builtin_amdgcn_readlane((uint32_t)m_off, j));
-        const uint8_t *src = ((fl & 2u) ? images : pyr) + off;
-        const bool aligned = !(fl & 2u) || a.aligned0;
-        const int xs = (x - 18) & ~3;
-        p_delta = (x - 18) - xs;
-        if (aligned && y >= 18 && y + 18 < lh && xs >= 0 && xs + 40 <= lw && pitch < (1 << 24)) {
-            // the whole 40 x 37 window lies inside the level: plain 32-bit loads
-            // (32-bit per-lane offsets from a uniform base: 24-bit
-            // multiply-adds and scalar-base addressing, no 64-bit lane math;
-            // 36 rows of a pitch below 2^24 stay below 2^32)
-            const uint8_t *base = src + (int64_t)(y - 18) * pitch + xs;
+        // (a global-memory pointer: rebuilt from an integer it would be a
+        // generic one, read with flat loads.  readlane returns a signed int:
+        // both halves go through uint32_t, or a low half with bit 31 set
+        // would be sign-extended into the high half)
+        typedef const __attribute__((address_space(1))) uint8_t gbyte;
+        const uint32_t a_hi = (uint32_t)__builtin_amdgcn_readlane((uint32_t)(m_addr >> 32), j);
+        const uint32_t a_lo = (uint32_t)__builtin_amdgcn_readlane((uint32_t)m_addr, j);
+        gbyte *addr = (gbyte *)(((uint64_t)a_hi << 32) | a_lo);
+        if (fl & 4u) {
+            // the whole window lies inside the level: plain 32-bit loads at
+            // 32-bit per-lane offsets from the uniform window address
+            // (24-bit multiply-adds, scalar-base addressing; 36 rows of a
+            // pitch below 2^24 stay below 2^32)
             const uint32_t step = (uint32_t)(pitch - 40);
 #pragma unroll
             for (int u = 0; u < 6; u++) {
                 const uint32_t off = __umul24((uint32_t)t_row(u), step) + 4u * (uint32_t)(lane + 64 * u);
-                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const uint32_t *)(base + off) : 0u;
+                p_v[u] = (lane + 64 * u < 37 * 10) ? *(const __attribute__((address_space(1))) uint32_t *)(addr + off) : 0u;
             }
         } else {
+            const uint32_t xy = __builtin_amdgcn_readlane(m_xy, j), wh = __builtin_amdgcn_readlane(m_wh, j);
+            const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
+            const int lw = (int)(wh & 0xFFFFu), lh = (int)(wh >> 16);
+            const int xs = (x - 18) & ~3;
 #pragma unroll
             for (int u = 0; u < 6; u++) {
                 p_v[u] = 0u;
                 if (lane + 64 * u < 37 * 10) {
                     const int gy = min(max(y - 18 + t_row(u), 0), lh - 1);
-                    p_v[u] = fetch4c(src + (int64_t)gy * pitch, xs + 4 * (lane + 64 * u - 10 * t_row(u)), lw);
+                    p_v[u] = fetch4c((const uint8_t *)(addr + (int64_t)gy * pitch), xs + 4 * (lane + 64 * u - 10 * t_row(u)), lw);
                 }
             }
         }
