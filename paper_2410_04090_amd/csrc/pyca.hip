@@ -240,7 +240,7 @@ __device__ __forceinline__ void find_bucket(const int *hist, int base, int need,
 // one block scan of the per-thread counts places every survivor.
 __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
     const ImageDev *__restrict__ imgs, const uint32_t *__restrict__ cell_keys, const uint32_t *__restrict__ rank,
-    vsfe_kp_soa kps, int32_t *__restrict__ kp_count, int n_max, int32_t *status) {
+    vsfe_kp_soa kps, int32_t *__restrict__ kp_count, int n_max, int32_t *status, PfaLevelTab tab) {
     __shared__ uint32_t s_rank[SEL_LDS_CELLS];
     __shared__ int hist[1024];
     __shared__ int wave_a[SEL_WAVES], wave_b[SEL_WAVES];
@@ -328,9 +328,16 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
         const LevelDev &lv = im.lv[l];
         const int li = (int)(i - (lv.cell_offset - base));
         const uint32_t key = cell_keys[base + i];
-        const int c = lv.cell, cy = li / lv.ncx, cx = li - cy * lv.ncx;
+        // li / ncx by a float reciprocal and one correction step (li <
+        // 2^24, so the estimate is off by at most one); off / c by the
+        // level's multiplier (off < 1024)
+        const int c = lv.cell;
+        int cy = (int)((float)li * __builtin_amdgcn_rcpf((float)lv.ncx));
+        int cx = li - cy * lv.ncx;
+        if (cx < 0) { cy--; cx += lv.ncx; }
+        if (cx >= lv.ncx) { cy++; cx -= lv.ncx; }
         const int off = 1023 - (int)(key & 1023u);
-        const int oy = off / c;
+        const int oy = (int)(__umul24((uint32_t)off, tab.mag[l]) >> 20);
         const int x = cx * c + (off - oy * c), y = cy * c + oy;
         if (slot < n_max) {
             const int64_t o = im.kp_offset + slot;
@@ -368,18 +375,18 @@ extern "C" int32_t pyca_cull_aggregate(const vsfe_ctx *ctx, const vsfe_batch *b,
     const vsfe_params &p = ctx->p;
     hipStream_t st = (hipStream_t)stream;
     uint32_t *rank = (uint32_t *)workspace;
+    PfaLevelTab tab;
+    memset(&tab, 0, sizeof(tab));
+    for (int l = 0; l < p.n_levels; l++) {
+        tab.inv[l] = 65536.0f / (float)ctx->scale_q16[l];
+        tab.mag[l] = (1u << 20) / (uint32_t)ctx->cell[l] + 1u;
+    }
     if (b->n_chunks > 0) {
         // every level's window (at most (2r+1)/s + 4 pixels wide) within 2 x 2 cells?
         bool fix2 = true;
         for (int l = 0; l < p.n_levels; l++) {
             const double s_l = ctx->scale_q16[l] / 65536.0;
             if ((2 * p.nms_radius + 1) / s_l + 3.0 > (double)ctx->cell[l]) fix2 = false;
-        }
-        PfaLevelTab tab;
-        memset(&tab, 0, sizeof(tab));
-        for (int l = 0; l < p.n_levels; l++) {
-            tab.inv[l] = 65536.0f / (float)ctx->scale_q16[l];
-            tab.mag[l] = (1u << 20) / (uint32_t)ctx->cell[l] + 1u;
         }
 #define VSFE_PFA_LAUNCH(R_)                                                                                       \
     do {                                                                                                          \
@@ -401,6 +408,6 @@ extern "C" int32_t pyca_cull_aggregate(const vsfe_ctx *ctx, const vsfe_batch *b,
         if (rc) return rc;
     }
     hipLaunchKernelGGL(select_compact_kernel, dim3(b->n_images), dim3(SEL_THREADS), 0, st, b->d_images, cell_keys,
-                       rank, *kps, kp_count, p.n_max, status);
+                       rank, *kps, kp_count, p.n_max, status, tab);
     return check_launch("pyca_cull_aggregate (select)");
 }
