@@ -460,9 +460,10 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     // texture) takes them in rounds, each screened and decided in full.
     for (int r0 = 0; r0 < qn; r0 += FT_QW) {
     {
-        // entry of bit b = 16 h + k: (wv + 4 k) << 7 | (lane + 64 h)
-        //                            = base + 512 k + 4 (b - k) = base + 4 b + 508 k
-        static_assert(DET_WAVES == 4 && FT_HALF == 64, "entry arithmetic assumes 4 waves, 64-lane halves");
+        // entry of bit b = 16 h + k: (wv + W k) << 7 | (lane + 64 h)
+        //     = base + 128 W k + 4 (b - k) = base + 4 b + (128 W - 4) k
+        static_assert(FT_HALF == 64, "entry arithmetic assumes 64-lane halves");
+        constexpr int EK = 128 * DET_WAVES - 4;
         const int ebase = (wv << 7) | lane;
         uint32_t mm = cm;
         int pos = incl - cnt;
@@ -470,13 +471,13 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
             while (mm) {
                 const int bit = __builtin_ctz(mm);
                 mm &= mm - 1;
-                q[pos++] = (uint16_t)(ebase + 4 * bit + 508 * (bit & 15));
+                q[pos++] = (uint16_t)(ebase + 4 * bit + EK * (bit & 15));
             }
         } else {
             while (mm) {
                 const int bit = __builtin_ctz(mm);
                 mm &= mm - 1;
-                if (pos >= r0 && pos < r0 + FT_QW) q[pos - r0] = (uint16_t)(ebase + 4 * bit + 508 * (bit & 15));
+                if (pos >= r0 && pos < r0 + FT_QW) q[pos - r0] = (uint16_t)(ebase + 4 * bit + EK * (bit & 15));
                 pos++;
             }
         }
