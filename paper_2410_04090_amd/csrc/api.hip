@@ -94,7 +94,7 @@ static int32_t plan_batch(const vsfe_params &p, int tile_w, int tile_h, int32_t 
     b->info.n_images = n;
     b->info.n_levels = L;
 
-    int64_t cell_at = 0, crf_at = 0, cell0_at = 0, pyr_at = 0, in_end = 0;
+    int64_t cell_at = 0, crf_at = 0, cell0_at = 0, pyr_at = 0, in_end = 0, row_at = 0;
     for (int i = 0; i < n; i++) {
         const int W = widths[i], H = heights[i];
         if (W < 1 || H < 1 || W > VSFE_MAX_DIM || H > VSFE_MAX_DIM || pitches[i] < W || offsets[i] < 0)
@@ -127,9 +127,13 @@ static int32_t plan_batch(const vsfe_params &p, int tile_w, int tile_h, int32_t 
             }
             lv.cell_offset = cell_at;
             lv.crf_offset = crf_at;
+            lv.row_tab = (int32_t)row_at;
+            row_at += lv.ncy;
             cell_at += (int64_t)lv.ncx * lv.ncy;
             crf_at += (int64_t)lv.w * lv.h;
         }
+        im.row_tab_end = (int32_t)row_at;
+        row_at += 1;                             // the entry after the last cell row
         im.n_cells = cell_at - im.cell_base;
         cell0_at += (int64_t)im.lv[0].ncx * im.lv[0].ncy;
     }
@@ -228,6 +232,7 @@ static int32_t plan_batch(const vsfe_params &p, int tile_w, int tile_h, int32_t 
     b->info.pyr_bytes = std::max<int64_t>(pyr_at, 256);
     b->info.crf_elems = crf_at;
     b->info.n_cells = cell_at;
+    b->n_row_tab = (int32_t)row_at;
     b->info.n_cells0 = cell0_at;
     b->info.kp_capacity = (int64_t)n * p.n_max;
     b->info.workspace_bytes = cell_at * 4 + 256;
@@ -384,6 +389,7 @@ int32_t vsfe_batch_destroy(vsfe_batch *b) {
     if (b->d_det_items) (void)hipFree(b->d_det_items);
     if (b->d_chunks) (void)hipFree(b->d_chunks);
     if (b->d_run) (void)hipFree(b->d_run);
+    if (b->d_row_tab) (void)hipFree(b->d_row_tab);
     cnn_release(b);
     delete b;
     return VSFE_OK;
@@ -416,6 +422,9 @@ int32_t vsfe_batch_create(const vsfe_ctx *ctx, int32_t n, const int32_t *widths,
     if (!rc) rc = upload(b->h_chunks, &b->d_chunks);
     if (!rc && b->info.n_cells > 0 && hipMalloc((void **)&b->d_run, (size_t)b->info.n_cells) != hipSuccess)
         rc = fail(VSFE_EHIP, "hipMalloc of the run-flag table failed");
+    if (!rc && b->n_row_tab > 0 &&
+        hipMalloc((void **)&b->d_row_tab, (size_t)b->n_row_tab * sizeof(int32_t)) != hipSuccess)
+        rc = fail(VSFE_EHIP, "hipMalloc of the row-start table failed");
     if (!rc) rc = cnn_setup(b);
     if (rc) {
         vsfe_batch_destroy(b);

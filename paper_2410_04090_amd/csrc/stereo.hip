@@ -5,7 +5,10 @@
 // order (level, cell row, cell column), so the candidates of a left
 // keypoint at level l and row y -- same level, |dy| <= row_band -- lie in
 // the contiguous run of cell rows floor((y - band) / c_l) ..
-// floor((y + band) / c_l), found by two binary searches.  Each candidate
+// floor((y + band) / c_l).  A first pass writes, for every cell row of every
+// right image, the index of its first keypoint (one thread per keypoint
+// fills the rows from the previous keypoint's row to its own), so that run
+// is two table reads.  Each candidate
 // with native-scale disparity d = x0_l - x0_r in [0, d_max] costs eight
 // popcounts; the least distance wins, ties to smaller |dy|, smaller d,
 // smaller index (ascending scan with strict comparisons).
@@ -18,13 +21,37 @@ struct StereoArgs {
     int n_max, n_pairs, d_max, match_th, band;
 };
 
-__device__ __forceinline__ int row_key(int level, int y, const StereoArgs &a) { return (level << 16) | (y / a.cell[level]); }
+// Row-start table of the right images: entry lv.row_tab + cy holds the
+// index of the first keypoint of cell row cy of level l, or of the next row
+// that has one (the rows of all levels are consecutive; entry row_tab_end is
+// the keypoint count).  Thread j of image ri writes the entries after the
+// previous keypoint's row up to its own row; thread count writes the rest.
+__global__ __launch_bounds__(256) void row_table_kernel(const ImageDev *__restrict__ imgs, vsfe_kp_soa kps,
+                                                        const int32_t *__restrict__ kp_count,
+                                                        int32_t *__restrict__ tab, StereoArgs a) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int pair = (int)(s / (a.n_max + 1));
+    const int j = (int)(s - (int64_t)pair * (a.n_max + 1));
+    if (pair >= a.n_pairs) return;
+    const ImageDev &im = imgs[2 * pair + 1];
+    const int nr = kp_count[2 * pair + 1];
+    if (j > nr) return;
+    auto entry = [&](int k) {               // table entry of keypoint k's cell row
+        const int64_t rs = im.kp_offset + k;
+        // (clamped into the image's table whatever the arrays hold)
+        const int l = min((int)kps.level[rs], im.n_levels - 1);
+        return im.lv[l].row_tab + min((int)kps.y[rs] / a.cell[l], im.lv[l].ncy - 1);
+    };
+    const int lo = j > 0 ? entry(j - 1) + 1 : im.lv[0].row_tab;
+    const int hi = j < nr ? entry(j) : im.row_tab_end;
+    for (int e = lo; e <= hi; e++) tab[e] = j;
+}
 
 __global__ __launch_bounds__(256) void stereo_kernel(const ImageDev *__restrict__ imgs, vsfe_kp_soa kps,
                                                      const int32_t *__restrict__ kp_count,
                                                      const uint32_t *__restrict__ desc, int32_t *__restrict__ midx,
                                                      uint16_t *__restrict__ mdist, int16_t *__restrict__ mdisp,
-                                                     StereoArgs a) {
+                                                     const int32_t *__restrict__ tab, StereoArgs a) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int pair = (int)(s / a.n_max);
     const int i = (int)(s - (int64_t)pair * a.n_max);
@@ -39,22 +66,13 @@ __global__ __launch_bounds__(256) void stereo_kernel(const ImageDev *__restrict_
 #pragma unroll
     for (int w = 0; w < 8; w++) d[w] = desc[lslot * 8 + w];
 
-    const int klo = row_key(level, max(y - a.band, 0), a), khi = row_key(level, y + a.band, a);
-    // first index with key >= klo
-    int lo = 0, hi = nr;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (row_key(kps.level[rbase + mid], kps.y[rbase + mid], a) < klo) lo = mid + 1;
-        else hi = mid;
-    }
-    const int start = lo;
-    hi = nr;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (row_key(kps.level[rbase + mid], kps.y[rbase + mid], a) <= khi) lo = mid + 1;
-        else hi = mid;
-    }
-    const int end = lo;
+    const LevelDev &rl = imgs[ri].lv[level];
+    const int c = a.cell[level];
+    const int cy_lo = max(y - a.band, 0) / c, cy_hi = min((y + a.band) / c, rl.ncy - 1);
+    // (clamped to [0, nr]: with keypoints out of canonical order some
+    // entries are not written, and no read may leave the image's slots)
+    const int start = min(max(tab[rl.row_tab + cy_lo], 0), nr);
+    const int end = min(max(tab[rl.row_tab + cy_hi + 1], start), nr);
 
     int best = -1, bd = 0, bdy = 0, bdisp = 0;
     for (int j = start; j < end; j++) {
@@ -107,7 +125,13 @@ extern "C" int32_t stereo_match(const vsfe_ctx *ctx, const vsfe_batch *b, const 
     a.band = ctx->p.row_band;
     const int64_t n = (int64_t)a.n_pairs * a.n_max;
     if (n <= 0) return VSFE_OK;
+    if (!b->d_row_tab) return fail(VSFE_EINVAL, "batch has no row-start table");
+    const int64_t nt = (int64_t)a.n_pairs * (a.n_max + 1);
+    hipLaunchKernelGGL(row_table_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       b->d_images, *kps, kp_count, b->d_row_tab, a);
+    rc = check_launch("stereo_match (row table)");
+    if (rc) return rc;
     hipLaunchKernelGGL(stereo_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       b->d_images, *kps, kp_count, desc, match_idx, match_dist, match_disp, a);
+                       b->d_images, *kps, kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
     return check_launch("stereo_match");
 }

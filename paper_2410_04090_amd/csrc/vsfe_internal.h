@@ -16,7 +16,7 @@ struct LevelDev {
     int32_t w, h, pitch, cell;
     int32_t ncx, ncy, scale_q16;
     int32_t xtab, ytab;    // first entries of the resampling tables (levels >= 1)
-    int32_t pad;
+    int32_t row_tab;       // row-start table entry of this level's cell row 0
     int64_t offset;        // level 0: into the input buffer, else into the pyramid buffer
     int64_t cell_offset;   // global index of the first cell of this level
     int64_t crf_offset;    // first element of this level in the response dump
@@ -24,7 +24,7 @@ struct LevelDev {
 static_assert(sizeof(LevelDev) == 64, "LevelDev layout");
 
 struct ImageDev {
-    int32_t w, h, n_levels, pad;
+    int32_t w, h, n_levels, row_tab_end;   // row_tab_end: the image's last row-start entry
     int64_t cell_base;     // first cell of the image (level 0)
     int64_t n_cells;       // cells over all levels
     int64_t cell0_offset;  // first level-0 cell in mask / logit arrays
@@ -124,6 +124,8 @@ struct vsfe_batch {
     std::vector<vsfe::CellChunk> h_chunks;
     vsfe::CellChunk *d_chunks = nullptr;
     uint8_t *d_run = nullptr;                    // per-cell run flags of the gated detector
+    int32_t n_row_tab = 0;                       // stereo: first keypoint of every cell row
+    int32_t *d_row_tab = nullptr;
     bool pairs_ok = false;                       // even count, equal pair sizes
     void *cnn = nullptr;                         // proposer plan (levels >= 4)
     vsfe_cnn_info info_cnn{};
