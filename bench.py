@@ -5,8 +5,9 @@ One step = one pass of the whole exact path (pyramid, FAST + Bounded
 Rectification with fused culling, pyramidal aggregation + cap, ORB
 orientation + rBRIEF, stereo matching) over one batch of synthetic stereo
 pairs already resident in HBM, replayed as one HIP graph.  Prints one JSON
-line; see the design doc for the workload, the algorithmic byte counts and the
-roofline definitions.
+line with the throughput, the dominant kernel's roofline figures (its
+algorithmic bytes per launch over its measured launch time, and the HBM
+bytes from the stored counter summary) and the oracle's host-core rate.
 """
 from __future__ import annotations
 
@@ -241,7 +242,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cfg5", choices=["cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--workload", default="batch64_1080p", choices=["pair_1241x376", "batch32_mixed", "batch64_1080p"])
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-procs", type=int, default=1,
@@ -258,8 +259,8 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); pairs are independent, "
-              "see DESIGN.md for how the batch would shard across GPUs", file=sys.stderr)
+        print("bench.py: one GPU only (--gpus 1); stereo pairs are independent, so a batch would "
+              "shard across GPUs by whole pairs, each GPU replaying its own graph", file=sys.stderr)
         sys.exit(2)
 
     from synth import configs, pattern as pat
@@ -330,7 +331,7 @@ def main():
     call_us = {k: time_call(f, reps, stream) for k, f in calls.items()}
     torch.cuda.synchronize()
 
-    # ---- algorithmic bytes: per call, whole batch
+    # ---- algorithmic bytes per call, whole batch: what each call must read and write
     L = wl.params.n_levels
     px_all = px_up = px_last = sum_l0 = 0
     n_cells = int(fe.info.n_cells)

@@ -13,9 +13,9 @@ of the exact path's keypoints, and does the same for a non-learned
 baseline (level-3 intensity range per cell); thresholds are stored per
 image size with the weights.
 
-    python -m paper_2410_04090_amd.train --pairs 50000 --out gpurun_out/proposer.npz
-    python -m paper_2410_04090_amd.train --scene hd --init gpurun_out/proposer.npz --pairs 8000 \\
-        --batch 16 --out gpurun_out/proposer_hd.npz
+    python -m paper_2410_04090_amd.train --pairs 50000 --out proposer.npz
+    python -m paper_2410_04090_amd.train --scene hd --init proposer.npz --pairs 8000 \\
+        --batch 16 --out proposer_hd.npz
 """
 from __future__ import annotations
 
@@ -246,7 +246,7 @@ def main():
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--pos-weight", type=float, default=1.0)
-    ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "proposer.npz"))
+    ap.add_argument("--out", default="proposer.npz")
     ap.add_argument("--resume", default=None, help="continue from a checkpoint (weights + Adam state)")
     ap.add_argument("--init", default=None, help="start from a checkpoint's weights with a fresh optimizer")
     ap.add_argument("--eval-only", action="store_true")

@@ -70,39 +70,40 @@ class Workload:
         return out
 
 
-def cfg1() -> Workload:
+def mono_752x480() -> Workload:
     """Single 752x480 image, one level, FAST-9 eps 20 with BR, 32x32 cells."""
     p = Params(eps_hi=20, eps_lo=-1, border=3, n_levels=1, pfa=0, n_max=4096,
                blur=0, d_max=0)
-    return Workload("cfg1_mono_752x480_L1", [(752, 480)], [1], p, stereo=False,
+    return Workload("mono_752x480_L1", [(752, 480)], [1], p, stereo=False,
                     describe=False)
 
 
-def cfg2() -> Workload:
+def pair_1241x376() -> Workload:
     """One rectified 1241x376 pair through the full 8-level pipeline."""
-    return Workload("cfg2_pair_1241x376_L8", [(1241, 376)], [2], Params())
+    return Workload("pair_1241x376_L8", [(1241, 376)], [2], Params())
 
 
-def cfg3() -> Workload:
+def batch32_mixed() -> Workload:
     """32 pairs, 8 each of 640x480, 752x480, 1241x376, 1280x720."""
     sizes = [(640, 480)] * 8 + [(752, 480)] * 8 + [(1241, 376)] * 8 + [(1280, 720)] * 8
-    return Workload("cfg3_batch32_mixed_L8", sizes, list(range(100, 132)), Params())
+    return Workload("batch32_mixed_L8", sizes, list(range(100, 132)), Params())
 
 
-def cfg4() -> Workload:
+def learned_1241x376() -> Workload:
     """Learned-proposal evaluation pairs at 1241x376 (held-out seeds)."""
-    return Workload("cfg4_learned_1241x376_L8", [(1241, 376)] * 8,
+    return Workload("learned_1241x376_L8", [(1241, 376)] * 8,
                     [2_000_000 + i for i in range(8)], Params())
 
 
-def cfg5() -> Workload:
+def batch64_1080p() -> Workload:
     """64 pairs of 1920x1080, 800 polygons, disparities 0..128."""
     p = Params(n_max=4000, d_max=128)
-    return Workload("cfg5_batch64_1920x1080_L8", [(1920, 1080)] * 64,
+    return Workload("batch64_1920x1080_L8", [(1920, 1080)] * 64,
                     list(range(200, 264)), p, n_polygons=800, max_disparity=128)
 
 
-WORKLOADS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4, "cfg5": cfg5}
+WORKLOADS = {"mono_752x480": mono_752x480, "pair_1241x376": pair_1241x376, "batch32_mixed": batch32_mixed,
+             "learned_1241x376": learned_1241x376, "batch64_1080p": batch64_1080p}
 
 
 def small_variant(w: Workload, scale: float) -> Workload:

@@ -128,7 +128,7 @@ def check_invariants(fe, params):
 def test_mixed_batch_full_size(fe_mod, pattern):
     """32 pairs of four sizes (640x480, 752x480, 1241x376, 1280x720): every
     pair against the oracle."""
-    wl = configs.cfg3()
+    wl = configs.batch32_mixed()
     say("case: mixed batch", wl.name)
     imgs = wl.images()
     fe = run_bench_config(fe_mod, wl, imgs, pattern)
@@ -142,7 +142,7 @@ def test_mixed_batch_full_size(fe_mod, pattern):
 def test_1080p_batch_full_size_sampled(fe_mod, pattern):
     """64 pairs of 1920x1080 with at most 4000 keypoints per image: four
     sampled pairs against the oracle, invariants on all."""
-    wl = configs.cfg5()
+    wl = configs.batch64_1080p()
     say("case: 1080p batch", wl.name)
     imgs = wl.images()
     fe = run_bench_config(fe_mod, wl, imgs, pattern)

@@ -64,15 +64,15 @@ def run_and_compare(fe_mod, imgs, params, pattern, full_stages=True, tile=None, 
         fe.close()
 
 
-def test_cfg1_mono_752x480(fe_mod, pattern):
-    w = configs.cfg1()
+def test_mono_752x480(fe_mod, pattern):
+    w = configs.mono_752x480()
     imgs = w.images()
     _, refs, _ = run_and_compare(fe_mod, imgs, w.params, pattern, describe=False)
     assert len(refs[0]["x"]) > 100
 
 
-def test_cfg2_pair_1241x376(fe_mod, pattern):
-    w = configs.cfg2()
+def test_pair_1241x376(fe_mod, pattern):
+    w = configs.pair_1241x376()
     _, refs, n_acc = run_and_compare(fe_mod, w.images(), w.params, pattern)
     assert len(refs[0]["x"]) > 500 and n_acc > 100
 
@@ -156,7 +156,7 @@ def test_gated_detection_matches_oracle(fe_mod, pattern):
 
 def test_deterministic_repeats(fe_mod, pattern):
     import torch
-    w = configs.cfg2()
+    w = configs.pair_1241x376()
     imgs = w.images()
     fe = fe_mod.Frontend(w.params, [(1241, 376)] * 2, pattern)
     try:
@@ -175,7 +175,7 @@ def test_deterministic_repeats(fe_mod, pattern):
 @pytest.mark.parametrize("overlap", [False, True])
 def test_graph_replay_matches_eager(fe_mod, pattern, overlap):
     import torch
-    w = configs.cfg2()
+    w = configs.pair_1241x376()
     imgs = w.images()
     fe = fe_mod.Frontend(w.params, [(1241, 376)] * 2, pattern)
     try:
