@@ -199,7 +199,7 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 __device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 // ceil(2^16 / d) for d = 1..32 (cell sides and cells per tile row): for
-// v < 128, (v * ceil(2^16 / d)) >> 16 = v / d exactly.
+// v < 2048, (v * ceil(2^16 / d)) >> 16 = v / d exactly.
 struct InvTable {
     uint32_t v[33];
 };
@@ -234,6 +234,12 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int c = lv.cell;
     const int nk = it.nkx * it.nky;
+    const uint32_t inv_c = c_inv16.v[c], inv_nkx = c_inv16.v[it.nkx];   // c, nkx <= 32
+    // global index of cell k of the tile (k < 2048, so k / nkx is exact by the reciprocal)
+    auto cell_index = [&](int k) {
+        const int ky = (int)(__umul24((uint32_t)k, inv_nkx) >> 16), kx = k - ky * it.nkx;
+        return lv.cell_offset + (int64_t)(it.cy0 + ky) * lv.ncx + (it.cx0 + kx);
+    };
     const int x0 = it.cx0 * c, y0 = it.cy0 * c;
     const int x1 = min(x0 + it.nkx * c, lv.w), y1 = min(y0 + it.nky * c, lv.h);
     const int tw = x1 - x0, th = y1 - y0;
@@ -250,8 +256,8 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     uint32_t mf0 = 1u, mf1 = 1u;
     if (mask) {
         const int k0 = tid, k1 = tid + DET_THREADS;
-        mf0 = k0 < nk ? mask[lv.cell_offset + (int64_t)(it.cy0 + k0 / it.nkx) * lv.ncx + (it.cx0 + k0 % it.nkx)] : 0u;
-        mf1 = k1 < nk ? mask[lv.cell_offset + (int64_t)(it.cy0 + k1 / it.nkx) * lv.ncx + (it.cx0 + k1 % it.nkx)] : 0u;
+        mf0 = k0 < nk ? mask[cell_index(k0)] : 0u;
+        mf1 = k1 < nk ? mask[cell_index(k1)] : 0u;
     }
     // an interior tile (every staged chunk inside the level, aligned rows)
     // loads without per-thread checks (uniform)
@@ -308,7 +314,7 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
         for (int w = 0; w < DET_WAVES; w++) any |= s_anyw[w];
         if (!any && !crf) {
             for (int k = tid; k < nk; k += DET_THREADS)
-                cell_keys[lv.cell_offset + (int64_t)(it.cy0 + k / it.nkx) * lv.ncx + (it.cx0 + k % it.nkx)] = 0;
+                cell_keys[cell_index(k)] = 0;
             return;
         }
     } else {
@@ -327,8 +333,7 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     const bool okh = FT_HALF + lane < tw && gxh >= B && gxh < lv.w - B;
     const us2 e2 = {(unsigned short)prm.eps_min, (unsigned short)prm.eps_min};
     const int ylo = max(B - y0, 0), yhi = min(lv.h - B - y0, th);
-    // v < 128: (v * ceil(2^16 / d)) >> 16 is v / d exactly (for d <= 256)
-    const uint32_t inv_c = c_inv16.v[c], inv_nkx = c_inv16.v[it.nkx];   // c, nkx <= 32
+    // v < 2048: (v * ceil(2^16 / d)) >> 16 is v / d exactly (for d <= 32)
     auto div_c = [&](int v) { return (int)(__umul24((uint32_t)v, inv_c) >> 16); };
     const int kxl = div_c(lane), kxh = div_c(FT_HALF + lane);
     uint32_t cm = 0;
@@ -388,7 +393,7 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
             for (int k = 0; k < FT_MAX_ROWS / DET_WAVES; k++) {
                 const int r = wv + DET_WAVES * k;
                 if (r >= th) break;                      // uniform
-                const int kr = (r / c) * it.nkx;
+                const int kr = (int)((uint32_t)(r * inv_c) >> 16) * it.nkx;   // r < 32: r / c exactly
                 gm |= (s_run[kr + ka] ? 1u : 0u) << k;
                 gm |= (s_run[kr + kb] ? 0x10000u : 0u) << k;
             }
@@ -579,8 +584,7 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     for (int k = tid; k < nk; k += DET_THREADS) {       // nk <= 128
         const uint32_t hi = s_hi[k], lo = s_lo[k];
         const uint32_t v = hi ? hi : (lo ? (lo | VSFE_KEY_FALLBACK) : 0u);
-        const int ky = (int)(__umul24((uint32_t)k, inv_nkx) >> 16), kx = k - ky * it.nkx;
-        cell_keys[lv.cell_offset + (int64_t)(it.cy0 + ky) * lv.ncx + (it.cx0 + kx)] = v;
+        cell_keys[cell_index(k)] = v;
     }
 }
 

@@ -3,7 +3,7 @@ exhaustively over the operand ranges the kernels guarantee (host arithmetic
 only; the GPU parity tests check the kernels that use them).
 
 * detector: v / d as (v * ceil(2^16 / d)) >> 16 for cell sides and cells per
-  tile row d <= 32 and tile offsets v < 128;
+  tile row d <= 32 and v < 2048 (tile offsets, cell numbers within a tile);
 * aggregation and selection: off / c as (off * (floor(2^20 / c) + 1)) >> 20
   for cell offsets off < 1024;
 * selection: li / ncx by a single-precision reciprocal (within one ulp of
@@ -14,8 +14,8 @@ only; the GPU parity tests check the kernels that use them).
 import numpy as np
 
 
-def test_reciprocal_16_exact_below_128():
-    v = np.arange(128, dtype=np.int64)
+def test_reciprocal_16_exact_below_2048():
+    v = np.arange(2048, dtype=np.int64)
     for d in range(1, 33):
         inv = (65535 + d) // d
         assert np.array_equal((v * inv) >> 16, v // d), d
