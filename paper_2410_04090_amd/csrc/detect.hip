@@ -389,13 +389,22 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
         if (it.nky == 1) {                               // one cell row (levels with c >= 16): per lane
             gm = (s_run[ka] ? 0xFFu : 0u) | (s_run[kb] ? 0xFF0000u : 0u);
         } else {
+            // run flags of the lane's two cells in each cell row j (bits j and
+            // 8 + j), read once; a pixel row then selects its cell row's bits
+            uint32_t rb = 0;
+#pragma unroll
+            for (int j = 0; j < DET_MAX_CELLS_Y; j++) {
+                if (j >= it.nky) break;                  // uniform
+                rb |= (s_run[j * it.nkx + ka] ? 1u : 0u) << j;
+                rb |= (s_run[j * it.nkx + kb] ? 0x100u : 0u) << j;
+            }
 #pragma unroll
             for (int k = 0; k < FT_MAX_ROWS / DET_WAVES; k++) {
                 const int r = wv + DET_WAVES * k;
                 if (r >= th) break;                      // uniform
-                const int kr = (int)((uint32_t)(r * inv_c) >> 16) * it.nkx;   // r < 32: r / c exactly
-                gm |= (s_run[kr + ka] ? 1u : 0u) << k;
-                gm |= (s_run[kr + kb] ? 0x10000u : 0u) << k;
+                const int j = (int)((uint32_t)(r * inv_c) >> 16);              // r < 32: r / c exactly
+                gm |= ((rb >> j) & 1u) << k;
+                gm |= ((rb >> (8 + j)) & 1u) << (16 + k);
             }
         }
         cm &= gm;
