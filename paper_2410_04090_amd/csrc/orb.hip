@@ -243,7 +243,9 @@ __global__ __launch_bounds__(256, 6) void orb_kernel(const ImageDev *__restrict_
 
     load_meta(0);
     fetch(0);
-    for (int64_t k = 0; first + k * nw < n_slots; k++) {
+    // (the slot advances by nw per iteration: an add, not a 64-bit multiply)
+    int64_t slot = first;
+    for (int64_t k = 0; slot < n_slots; k++, slot += nw) {
         const bool active = p_act;
         const int delta = p_delta;
         if (active) {
@@ -289,7 +291,6 @@ __global__ __launch_bounds__(256, 6) void orb_kernel(const ImageDev *__restrict_
 #pragma unroll
             for (int rnd = 0; rnd < 4; rnd++) qv[rnd] = pr[rnd * 64 + lane];
         }
-        const int64_t slot = first + k * nw;
         const int jn = (int)((k + 1) & 63);
         if (jn == 0) load_meta(k + 1);
         fetch(jn);
