@@ -79,6 +79,8 @@ def _declare(L):
     L.or_cull_level.argtypes = [p, i32, i32, i32, C.POINTER(OrParams), p, p]
     L.or_detect.argtypes = [p, i32, i32, C.POINTER(OrParams), p, C.POINTER(OrKps)]
     L.or_detect.restype = i32
+    L.or_cell_runs.argtypes = [i32, i32, i32, i32, i32, i32, i32, p]
+    L.or_cell_runs.restype = i32
     L.or_pfa_from_records.argtypes = [i32, p, p, p, p, i32, i32, i32, i32, i32, p, p, p]
     L.or_pfa_from_records.restype = i32
     L.or_blur_level.argtypes = [p, i32, i32, p]
@@ -241,6 +243,12 @@ def _total_cells(W, H, pp):
         c = cell_size(pp.cell0, l)
         t += ((w + c - 1) // c) * ((h + c - 1) // c)
     return t
+
+
+def cell_runs(level, cx, cy, c, W0, H0, cell0, mask0) -> bool:
+    """Learned gating footprint test of one level-l cell (mask0: level-0 cells)."""
+    m = np.ascontiguousarray(mask0, dtype=np.uint8)
+    return bool(lib().or_cell_runs(level, cx, cy, c, W0, H0, cell0, _ptr(m)))
 
 
 def pfa_from_records(level, x0, y0, resp, W, H, n_levels, nms_mode=0, nms_radius=1):

@@ -87,7 +87,7 @@ static int rank_cmp(const void *a, const void *b) {
     return p->idx < q->idx ? -1 : (p->idx > q->idx);
 }
 
-static int cell_runs(int32_t l, int32_t cx, int32_t cy, int32_t c, int32_t W0, int32_t H0,
+int32_t or_cell_runs(int32_t l, int32_t cx, int32_t cy, int32_t c, int32_t W0, int32_t H0,
                      int32_t cell0, const uint8_t *mask0) {
     if (!mask0) return 1;
     int64_t S = or_scale_q16(l);
@@ -141,7 +141,7 @@ int32_t or_detect(const uint8_t *pyr, int32_t W, int32_t H, const or_params *p,
         for (int32_t cy = 0; cy < ncy; cy++)
             for (int32_t cx = 0; cx < ncx; cx++) {
                 uint32_t k = key[cy * ncx + cx];
-                if (!k || !cell_runs(l, cx, cy, c, W, H, p->cell0, cell_mask0)) continue;
+                if (!k || !or_cell_runs(l, cx, cy, c, W, H, p->cell0, cell_mask0)) continue;
                 int32_t idx = 1023 - (int32_t)(k & 1023u);
                 R_level[n] = l;
                 R_x[n] = cx * c + idx % c;

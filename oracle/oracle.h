@@ -68,6 +68,11 @@ typedef struct {
 int32_t or_detect(const uint8_t *pyr, int32_t W, int32_t H, const or_params *p,
                   const uint8_t *cell_mask0, or_kps *out);
 
+/* Learned gating: does level-l cell (cx, cy) of side c run under the level-0
+ * cell mask (ncx0 x ncy0 bytes, row-major)?  1 when mask0 is NULL. */
+int32_t or_cell_runs(int32_t l, int32_t cx, int32_t cy, int32_t c, int32_t W0, int32_t H0,
+                     int32_t cell0, const uint8_t *mask0);
+
 /* PFA from a given per-cell key list (used by the figure replay as well). */
 int32_t or_pfa_from_records(int32_t n, const int32_t *level, const int32_t *x0,
                             const int32_t *y0, const int32_t *resp, int32_t W, int32_t H,

@@ -75,6 +75,40 @@ def test_pyramid_vs_float_bilinear():
         assert np.mean(diff) < 0.6
 
 
+def _q8_positions(n_dst, n_src):
+    """Half-pixel-centre source coordinate of every output index,
+    (o + 1/2) n_src / n_dst - 1/2, floored to a multiple of 1/256."""
+    from fractions import Fraction
+    out = []
+    for o in range(n_dst):
+        u = (Fraction(2 * o + 1) * n_src / n_dst - 1) / 2
+        out.append(float(Fraction(int(np.floor(u * 256)), 256)))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("seed,W,H", [(1, 61, 47), (2, 300, 200), (3, 97, 256), (4, 1241, 40)])
+def test_pyramid_level_is_rounded_bilinear_exactly(seed, W, H):
+    """Each level, taken from the oracle's previous level, equals scipy's
+    bilinear value at the Q8-floored half-pixel-centre coordinate rounded
+    half up, exactly.  Every product of a Q8 weight and a byte is exact in
+    float64, so scipy's value is the exact rational one; exact halves occur
+    (asserted), so a round-half-down or a truncating slip fails here."""
+    rng = np.random.default_rng(seed)
+    img = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    levels = oracle.pyramid(img, 6)
+    ties = 0
+    for l in range(1, 6):
+        src, dst = levels[l - 1].astype(np.float64), levels[l]
+        h, w = dst.shape
+        sh, sw = src.shape
+        gy, gx = np.meshgrid(_q8_positions(h, sh), _q8_positions(w, sw), indexing="ij")
+        v = ndimage.map_coordinates(src, [gy, gx], order=1, mode="nearest", prefilter=False)
+        ref = np.floor(v + 0.5)
+        assert np.array_equal(ref, dst.astype(np.float64)), (l, np.argwhere(ref != dst)[:3])
+        ties += int(np.sum(v - np.floor(v) == 0.5))
+    assert ties > 0
+
+
 def test_pyramid_ramp_exact_to_one():
     """A linear ramp is resampled to the ramp at the mapped coordinate."""
     x = np.arange(256, dtype=np.float64)
