@@ -137,6 +137,10 @@ static int32_t plan_batch(const vsfe_params &p, int tile_w, int tile_h, int32_t 
         im.n_cells = cell_at - im.cell_base;
         cell0_at += (int64_t)im.lv[0].ncx * im.lv[0].ncy;
     }
+    // the proposer's 32-bit prefix tables must hold the batch (before any
+    // per-tile work list is built)
+    rc = cnn_plan_check(b);
+    if (rc) return rc;
     // resampling tables, one per distinct (source size, level): entry o holds
     // the floored Q8 source coordinate of output o (index | weight << 16),
     // weight forced to 0 where the right / bottom neighbour is clamped

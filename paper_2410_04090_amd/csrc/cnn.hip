@@ -6,18 +6,32 @@
 //   x = (I_3 - 128) / 128 -> conv3x3 s2 (1 -> 16) -> ReLU -> conv3x3 s2
 //   (16 -> 32) -> ReLU -> conv3x3 s2 (32 -> 32) -> ReLU -> conv1x1 (32 -> 1).
 // Padding 1, ceil(in / 2) outputs per axis.  Parameters are one flat
-// vector, OIHW weights followed by biases per layer.  Weights and stored
-// activations are bfloat16 (NHWC), sums are float32.
+// vector, OIHW weights followed by biases per layer; the kernels read its
+// bfloat16 copy, so the network evaluated is the bfloat16-valued one.
 //
-//  * conv1 (K = 9 taps, padded to 16) runs on v_mfma_f32_16x16x16_bf16;
+// Precision.  Every product runs on the bfloat16 matrix cores with float32
+// accumulation.  The input (I - 128) / 128 and the weights are exact in
+// bfloat16; an activation is carried as two bfloat16 values, its rounding
+// hi and the rounding of the remainder lo (hi + lo holds about 16
+// significant bits), and each convolution adds W hi and W lo in separate
+// accumulator chains.  With one bfloat16 per activation the logits of the
+// trained networks differ from a float32 forward by up to 0.03; with the
+// pair they stay within 1e-2 (about 1e-4 in practice).  The 1x1 head reads
+// conv3's float32 output directly.
+//
+//  * conv1 (K = 9 taps) runs on v_mfma_f32_16x16x16_bf16: lane group g
+//    takes tap row g as the K slots (input columns 2x - 2 .. 2x + 1, the
+//    first with a zero weight, so a lane reads two aligned dwords);
 //  * conv2 (K = 144) and conv3 (K = 288) are implicit GEMMs on
-//    v_mfma_f32_16x16x32_bf16: one wave computes 32 channels x 16 output
-//    pixels, each lane feeding 8 consecutive channels of one tap as its
-//    K slice (weights repacked to [co][tap][ci]); the 1x1 head is fused in
-//    conv3's epilogue with a shuffle reduction over the channel groups;
+//    v_mfma_f32_16x16x32_bf16 (conv2's ninth tap on 16x16x16): weights are
+//    the A operand (row = output channel), activations the B operand
+//    (column = output pixel, 8 channels of one tap per lane);
 //  * inference (cnn_propose) runs the three layers and the head fused in
-//    one kernel per 4 x 8 tile of grid positions, activations in LDS; the
-//    layer-by-layer kernels (cnn_forward) keep the activations for training;
+//    one kernel per 4 x 8 tile of grid positions, activations in LDS in an
+//    even / odd column split layout (stride-2 reads of 16 consecutive
+//    output pixels hit consecutive 16-byte entries); the layer-by-layer
+//    kernels (cnn_forward) keep float32 activations for training and split
+//    them the same way, so both give bit-identical logits;
 //  * cell logits: per native-scale cell, the maximum over the grid
 //    positions whose projected centre ((8 j + 4) S_3 + 2^15) >> 16 falls in
 //    it (a cell with none is always kept);
@@ -56,10 +70,61 @@ struct CnnPlan {
 };
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf(uint16_t v) { return __builtin_bit_cast(float, (uint32_t)v << 16); }
 __device__ __forceinline__ uint16_t to_bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ float bf_lo(uint32_t v) { return __builtin_bit_cast(float, v << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t v) { return __builtin_bit_cast(float, v & 0xFFFF0000u); }
+
+// two floats as packed bfloat16 (round to nearest even): v_cvt_pk_bf16_f32
+__device__ __forceinline__ uint32_t pk_bf(float a, float b) {
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+// value / remainder pair of two activations: hi = bf16(v), lo = bf16(v - hi)
+__device__ __forceinline__ void split2(float a, float b, uint32_t *hi, uint32_t *lo) {
+    const uint32_t h = pk_bf(a, b);
+    *hi = h;
+    *lo = pk_bf(a - bf_lo(h), b - bf_hi(h));
+}
+
+// 4 activations (one lane's accumulator after bias and ReLU) as hi / lo pairs
+__device__ __forceinline__ void split4(f32x4 v, uint2 *hi, uint2 *lo) {
+    split2(v[0], v[1], &hi->x, &lo->x);
+    split2(v[2], v[3], &hi->y, &lo->y);
+}
+
+// 8 float32 activations as hi / lo bfloat16x8 operands
+__device__ __forceinline__ void split8(float4 a, float4 b, uint4 *hi, uint4 *lo) {
+    split2(a.x, a.y, &hi->x, &lo->x);
+    split2(a.z, a.w, &hi->y, &lo->y);
+    split2(b.x, b.y, &hi->z, &lo->z);
+    split2(b.z, b.w, &hi->w, &lo->w);
+}
+
+__device__ __forceinline__ f32x4 relu4(f32x4 v) {
+    f32x4 r;
+#pragma unroll
+    for (int i = 0; i < 4; i++) r[i] = fmaxf(v[i], 0.0f);
+    return r;
+}
+
+// the input (I - 128) / 128 of byte b of v: exact in float32 and bfloat16
+__device__ __forceinline__ float x_byte(uint32_t v, int b) {
+    float f;
+    switch (b) {
+        case 0: f = (float)(v & 255u); break;
+        case 1: f = (float)((v >> 8) & 255u); break;
+        case 2: f = (float)((v >> 16) & 255u); break;
+        default: f = (float)(v >> 24); break;
+    }
+    return fmaf(f, 1.0f / 128.0f, -1.0f);
+}
 
 // largest i with pre[i] <= g (pre is nondecreasing, pre[0] = 0)
 __device__ __forceinline__ int find_image(const int32_t *pre, int n, int64_t g) {
@@ -72,7 +137,25 @@ __device__ __forceinline__ int find_image(const int32_t *pre, int n, int64_t g) 
     return lo;
 }
 
-// --------------------------------------------------------------- forward
+__device__ __forceinline__ f32x4 mfma16(i16x4 a, i16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma32(uint4 a, uint4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+                                                  0);
+}
+__device__ __forceinline__ i16x4 as_i16x4(uint2 v) { return __builtin_bit_cast(i16x4, v); }
+
+__device__ __forceinline__ f32x4 splat4(float v) {
+    const f32x4 r = {v, v, v, v};
+    return r;
+}
+
+// ------------------------------------------------------------------ forward
+// MFMA lane layout (16 x 16 output tiles): lane l works on output pixel
+// l % 16 and K slice g = l / 16; its accumulator holds output channels
+// 4 g .. 4 g + 3 (+ 16 for the second 16-channel block).
+
 // Repack conv2 / conv3 weights from OIHW to [co][tap][ci] (bf16).
 __global__ void cnn_pack_kernel(const uint16_t *__restrict__ prm, uint16_t *__restrict__ wp2, uint16_t *__restrict__ wp3) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -86,323 +169,403 @@ __global__ void cnn_pack_kernel(const uint16_t *__restrict__ prm, uint16_t *__re
     }
 }
 
-// All three convolutions run on MFMA with the weights as the A operand
-// (row = output channel) and the activations as the B operand (column =
-// output pixel), so each lane ends with 4 consecutive channels of one pixel
-// and stores them as one 8-byte NHWC write.  Lane l: pixel l % 16, K slice
-// (l / 16); accumulator r of lane l is channel 4 (l / 16) + r.  Both forward
-// paths use the helpers below, so their activations and logits are
-// bit-identical.
-//
-// conv1 (1 -> 16, K = 9 taps zero-padded to 16) on v_mfma_f32_16x16x16_bf16;
-// the input x = (I - 128) / 128 is exact in bfloat16.
-typedef short i16x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ uint16_t x_bf(int v) { return to_bf((float)(v - 128) * (1.0f / 128.0f)); }
-
-// A operand of conv1: w1[c][k] for channel c = lane % 16 and the lane's 4 taps
-__device__ __forceinline__ i16x4 conv1_weights(const uint16_t *prm, int lane) {
-    const int c = lane & 15, k0 = 4 * (lane >> 4);
-    i16x4 w;
+// conv1 A operand: lane (channel c = l % 16, group g = l / 16).  Group g < 3
+// holds tap row g as K slots (0, w[g][0], w[g][1], w[g][2]); group 3 is zero.
+__device__ __forceinline__ i16x4 conv1_a(const uint16_t *prm, int lane) {
+    const int c = lane & 15, g = lane >> 4;
+    i16x4 w = {0, 0, 0, 0};
+    if (g < 3) {
 #pragma unroll
-    for (int j = 0; j < 4; j++) w[j] = (short)(k0 + j < 9 ? prm[P_W1 + c * 9 + k0 + j] : 0);
+        for (int kx = 0; kx < 3; kx++) w[kx + 1] = (short)prm[P_W1 + c * 9 + g * 3 + kx];
+    }
     return w;
 }
 
-__device__ __forceinline__ f32x4 conv1_mfma(i16x4 w, i16x4 x) {
-    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, x, zero, 0, 0, 0);
-}
-
-// bias + ReLU + bfloat16 of 4 consecutive channels, packed for one 8-byte store
-__device__ __forceinline__ uint2 relu_pack4(f32x4 acc, const float *bias) {
-    uint16_t v[4];
+// Weights of one 16-channel block (rows co0 .. co0 + 15) of conv2: four
+// 32-wide K chunks (taps 2c and 2c + 1, 16 channels each; lane group g takes
+// tap 2c + g / 2, channels 8 (g & 1) .. + 7) and tap 8 on 16 K (channels
+// 4 g .. 4 g + 3).
+struct W2 {
+    uint4 c[4];
+    uint2 t8;
+};
+__device__ __forceinline__ W2 conv2_a(const uint16_t *wp2, int lane, int co0) {
+    const int m = lane & 15, g = lane >> 4;
+    W2 w;
 #pragma unroll
-    for (int r = 0; r < 4; r++) v[r] = to_bf(fmaxf(acc[r] + bias[r], 0.0f));
-    return make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16));
+    for (int c = 0; c < 4; c++) w.c[c] = *(const uint4 *)(wp2 + ((co0 + m) * 9 + 2 * c + (g >> 1)) * 16 + 8 * (g & 1));
+    w.t8 = *(const uint2 *)(wp2 + ((co0 + m) * 9 + 8) * 16 + 4 * g);
+    return w;
 }
 
-__device__ __forceinline__ float bf_lo(uint32_t v) { return bf((uint16_t)(v & 0xFFFFu)); }
-__device__ __forceinline__ float bf_hi(uint32_t v) { return bf((uint16_t)(v >> 16)); }
+// conv3 weights of one 16-channel block: tap t, lane group g -> channels 8 g .. 8 g + 7
+struct W3 {
+    uint4 t[9];
+};
+__device__ __forceinline__ W3 conv3_a(const uint16_t *wp3, int lane, int co0) {
+    const int m = lane & 15, g = lane >> 4;
+    W3 w;
+#pragma unroll
+    for (int t = 0; t < 9; t++) w.t[t] = *(const uint4 *)(wp3 + ((co0 + m) * 9 + t) * 32 + 8 * g);
+    return w;
+}
 
-// 1x1 head partial of one lane (its 8 channels), fixed order
-__device__ __forceinline__ float head_part(uint2 p0, uint2 p1, const float *h0, const float *h1) {
+// B operands of one conv2 output pixel (per lane: its K slice), value and
+// remainder parts
+struct B2 {
+    uint4 h[4], l[4];
+    uint2 h8, l8;
+};
+struct B3 {
+    uint4 h[9], l[9];
+};
+
+// conv2 on the pair chains of both 16-channel blocks; the order of the
+// products (hi chain from the bias, lo chain from zero, tap by tap, then
+// hi + lo) is the same in the fused and layer-by-layer kernels
+__device__ __forceinline__ void conv2_mfma(const W2 &wa, const W2 &wb, const B2 &b, f32x4 bias_a, f32x4 bias_b,
+                                           f32x4 *va, f32x4 *vb) {
+    f32x4 ah = bias_a, bh = bias_b, al = splat4(0.f), bl = splat4(0.f);
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        ah = mfma32(wa.c[c], b.h[c], ah);
+        bh = mfma32(wb.c[c], b.h[c], bh);
+        al = mfma32(wa.c[c], b.l[c], al);
+        bl = mfma32(wb.c[c], b.l[c], bl);
+    }
+    ah = mfma16(as_i16x4(wa.t8), as_i16x4(b.h8), ah);
+    bh = mfma16(as_i16x4(wb.t8), as_i16x4(b.h8), bh);
+    al = mfma16(as_i16x4(wa.t8), as_i16x4(b.l8), al);
+    bl = mfma16(as_i16x4(wb.t8), as_i16x4(b.l8), bl);
+    *va = ah + al;
+    *vb = bh + bl;
+}
+
+// conv3 of one 16-channel block
+__device__ __forceinline__ f32x4 conv3_mfma(const W3 &w, const B3 &b, f32x4 bias) {
+    f32x4 h = bias, l = splat4(0.f);
+#pragma unroll
+    for (int t = 0; t < 9; t++) {
+        h = mfma32(w.t[t], b.h[t], h);
+        l = mfma32(w.t[t], b.l[t], l);
+    }
+    return h + l;
+}
+
+// per-lane biases (the accumulator's start): channels at + 4 g .. + 3
+__device__ __forceinline__ f32x4 conv_bias(const uint16_t *prm, int at, int lane) {
+    const int g = lane >> 4;
+    f32x4 b;
+#pragma unroll
+    for (int r = 0; r < 4; r++) b[r] = bf(prm[at + 4 * g + r]);
+    return b;
+}
+
+// 1x1 head partial of one 16-channel block (after ReLU): sum over the
+// lane's 4 channels, then over the 4 lane groups (fixed order); every lane
+// of column m ends with the block's sum for pixel m
+__device__ __forceinline__ float head16(f32x4 a, const uint16_t *prm, int co0, int lane) {
+    const int g = lane >> 4;
     float s = 0.f;
-    s += h0[0] * bf_lo(p0.x);
-    s += h0[1] * bf_hi(p0.x);
-    s += h0[2] * bf_lo(p0.y);
-    s += h0[3] * bf_hi(p0.y);
-    s += h1[0] * bf_lo(p1.x);
-    s += h1[1] * bf_hi(p1.x);
-    s += h1[2] * bf_lo(p1.y);
-    s += h1[3] * bf_hi(p1.y);
+#pragma unroll
+    for (int r = 0; r < 4; r++) s = fmaf(bf(prm[P_W4 + co0 + 4 * g + r]), a[r], s);
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
     return s;
 }
 
-// One wave: 16 consecutive conv1 pixels of one image (row-major), NHWC out.
+// ---- layer-by-layer kernels (training): one wave = 16 consecutive output
+// pixels of one image (row-major), float32 NHWC activations
+
 __global__ __launch_bounds__(256) void cnn_conv1_kernel(const CnnImg *__restrict__ imgs,
                                                         const int32_t *__restrict__ pre_tiles, int n,
                                                         int64_t total_tiles, const uint8_t *__restrict__ pyr,
-                                                        const uint16_t *__restrict__ prm, uint16_t *__restrict__ a1) {
+                                                        const uint16_t *__restrict__ prm, float *__restrict__ a1) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
     if (tile >= total_tiles) return;
     const int i = find_image(pre_tiles, n, tile);
     const CnnImg im = imgs[i];
     const int npx = im.w1 * im.h1;
-    const int m = lane & 15, grp = lane >> 4;
+    const int m = lane & 15, g = lane >> 4;
     const int pm = (int)(tile - pre_tiles[i]) * 16 + m;
     const int oy = pm / im.w1, ox = pm - oy * im.w1;
-    i16x4 x;
+    // K slots of group g: tap row g, input columns 2 ox - 2 .. 2 ox + 1
+    float x[4] = {0.f, 0.f, 0.f, 0.f};
+    const int iy = 2 * oy + (g < 3 ? g : 2) - 1;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-        const int k = 4 * grp + j;
-        const int iy = 2 * oy + k / 3 - 1, ix = 2 * ox + k % 3 - 1;
-        const bool in = pm < npx && k < 9 && iy >= 0 && iy < im.h3 && ix >= 0 && ix < im.w3;
-        x[j] = (short)(in ? x_bf(pyr[im.lvl3 + (int64_t)iy * im.pitch3 + ix]) : 0);
-    }
-    const f32x4 acc = conv1_mfma(conv1_weights(prm, lane), x);
-    float bias[4];
-#pragma unroll
-    for (int r = 0; r < 4; r++) bias[r] = bf(prm[P_B1 + 4 * grp + r]);
-    if (pm < npx) *(uint2 *)(a1 + (im.px1 + pm) * 16 + 4 * grp) = relu_pack4(acc, bias);
-}
-
-// Implicit-GEMM 3x3 stride-2 convolution CIN -> 32: K chunks of 32 (conv2:
-// pairs of taps x 16 channels, the last padded; conv3: one tap x 32
-// channels); A = packed weights [co][tap][ci], B = 8 channels of one tap of
-// the lane's pixel.  Returns through acc0 (channels 0..15) and acc1 (16..31).
-template <int CIN>
-__device__ __forceinline__ void conv_weights(const uint16_t *wp, int lane, uint4 *w0, uint4 *w1) {
-    constexpr int NCH = CIN == 16 ? 5 : 9;
-    const int m = lane & 15, grp = lane >> 4;
-#pragma unroll
-    for (int c = 0; c < NCH; c++) {
-        const int t = CIN == 16 ? 2 * c + (grp >> 1) : c;
-        const int ci0 = CIN == 16 ? 8 * (grp & 1) : 8 * grp;
-        w0[c] = w1[c] = make_uint4(0, 0, 0, 0);
-        if (t < 9) {
-            w0[c] = *(const uint4 *)(wp + ((m * 9 + t) * CIN + ci0));
-            w1[c] = *(const uint4 *)(wp + (((m + 16) * 9 + t) * CIN + ci0));
+        const int ix = 2 * ox - 2 + j;
+        if (pm < npx && g < 3 && iy >= 0 && iy < im.h3 && ix >= 0 && ix < im.w3) {
+            const uint32_t v = pyr[im.lvl3 + (int64_t)iy * im.pitch3 + ix];
+            x[j] = x_byte(v, 0);
         }
     }
+    const uint2 xb = make_uint2(pk_bf(x[0], x[1]), pk_bf(x[2], x[3]));
+    const f32x4 acc = relu4(mfma16(conv1_a(prm, lane), as_i16x4(xb), conv_bias(prm, P_B1, lane)));
+    if (pm < npx) *(f32x4 *)(a1 + (im.px1 + pm) * 16 + 4 * g) = acc;
 }
 
-__device__ __forceinline__ void conv_mfma2(uint4 xv, uint4 w0, uint4 w1, f32x4 &acc0, f32x4 &acc1) {
-    const bf16x8 x = __builtin_bit_cast(bf16x8, xv);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w0), x, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w1), x, acc1, 0, 0, 0);
+// 8 float32 channels at (y, x) of an NHWC map, zero outside
+__device__ __forceinline__ void load8(const float *a, int C, int64_t base, int w, int h, int y, int x, int ci0,
+                                      bool ok, float4 *p, float4 *q) {
+    *p = make_float4(0.f, 0.f, 0.f, 0.f);
+    *q = *p;
+    if (ok && y >= 0 && y < h && x >= 0 && x < w) {
+        const float *s = a + (base + (int64_t)y * w + x) * C + ci0;
+        *p = *(const float4 *)s;
+        *q = *(const float4 *)(s + 4);
+    }
 }
 
-template <int CIN, bool HEAD>
-__global__ __launch_bounds__(256) void cnn_conv_mfma_kernel(const CnnImg *__restrict__ imgs,
-                                                            const int32_t *__restrict__ pre_tiles, int n,
-                                                            int64_t total_tiles, const uint16_t *__restrict__ ain,
-                                                            uint16_t *__restrict__ aout, const uint16_t *__restrict__ wp,
-                                                            const uint16_t *__restrict__ prm, float *__restrict__ z) {
-    constexpr int NCH = CIN == 16 ? 5 : 9;
+__global__ __launch_bounds__(256) void cnn_conv2_kernel(const CnnImg *__restrict__ imgs,
+                                                        const int32_t *__restrict__ pre_tiles, int n,
+                                                        int64_t total_tiles, const float *__restrict__ a1,
+                                                        float *__restrict__ a2, const uint16_t *__restrict__ wp2,
+                                                        const uint16_t *__restrict__ prm) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
     if (tile >= total_tiles) return;
     const int i = find_image(pre_tiles, n, tile);
     const CnnImg im = imgs[i];
-    const int in_w = CIN == 16 ? im.w1 : im.w2, in_h = CIN == 16 ? im.h1 : im.h2;
-    const int out_w = CIN == 16 ? im.w2 : im.w4, out_h = CIN == 16 ? im.h2 : im.h4;
-    const int64_t in_base = CIN == 16 ? im.px1 : im.px2, out_base = CIN == 16 ? im.px2 : im.px4;
-    const int npx = out_w * out_h;
-    const int m = lane & 15, grp = lane >> 4;
+    const int npx = im.w2 * im.h2;
+    const int m = lane & 15, g = lane >> 4;
     const int pm = (int)(tile - pre_tiles[i]) * 16 + m;
     const bool valid = pm < npx;
-    const int oy = valid ? pm / out_w : 0, ox = valid ? pm - oy * out_w : 0;
-    uint4 w0[NCH], w1[NCH];
-    conv_weights<CIN>(wp, lane, w0, w1);
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    const int oy = valid ? pm / im.w2 : 0, ox = valid ? pm - oy * im.w2 : 0;
+    B2 b;
 #pragma unroll
-    for (int c = 0; c < NCH; c++) {
-        const int t = CIN == 16 ? 2 * c + (grp >> 1) : c;
-        const int ci0 = CIN == 16 ? 8 * (grp & 1) : 8 * grp;
-        uint4 xv = make_uint4(0, 0, 0, 0);
-        if (t < 9) {
-            const int iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
-            if (valid && iy >= 0 && iy < in_h && ix >= 0 && ix < in_w)
-                xv = *(const uint4 *)(ain + ((in_base + (int64_t)iy * in_w + ix) * CIN + ci0));
-        }
-        conv_mfma2(xv, w0[c], w1[c], acc0, acc1);
+    for (int c = 0; c < 4; c++) {
+        const int t = 2 * c + (g >> 1);
+        float4 p, q;
+        load8(a1, 16, im.px1, im.w1, im.h1, 2 * oy + t / 3 - 1, 2 * ox + t % 3 - 1, 8 * (g & 1), valid, &p, &q);
+        split8(p, q, &b.h[c], &b.l[c]);
     }
-    const int bias_at = CIN == 16 ? P_B2 : P_B3;
-    float b0[4], b1[4];
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-        b0[r] = bf(prm[bias_at + 4 * grp + r]);
-        b1[r] = bf(prm[bias_at + 16 + 4 * grp + r]);
+    {
+        float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int y = 2 * oy + 1, x = 2 * ox + 1;
+        if (valid && y < im.h1 && x < im.w1) p = *(const float4 *)(a1 + (im.px1 + (int64_t)y * im.w1 + x) * 16 + 4 * g);
+        split2(p.x, p.y, &b.h8.x, &b.l8.x);
+        split2(p.z, p.w, &b.h8.y, &b.l8.y);
     }
-    const uint2 v0 = relu_pack4(acc0, b0), v1 = relu_pack4(acc1, b1);
+    const W2 wa = conv2_a(wp2, lane, 0), wb = conv2_a(wp2, lane, 16);
+    f32x4 va, vb;
+    conv2_mfma(wa, wb, b, conv_bias(prm, P_B2, lane), conv_bias(prm, P_B2 + 16, lane), &va, &vb);
     if (valid) {
-        *(uint2 *)(aout + (out_base + pm) * 32 + 4 * grp) = v0;
-        *(uint2 *)(aout + (out_base + pm) * 32 + 16 + 4 * grp) = v1;
-    }
-    if (HEAD) {
-        float h0[4], h1[4];
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            h0[r] = bf(prm[P_W4 + 4 * grp + r]);
-            h1[r] = bf(prm[P_W4 + 16 + 4 * grp + r]);
-        }
-        const float part = head_part(v0, v1, h0, h1);
-        if (grp == 0 && valid) z[out_base + pm] = part + bf(prm[P_B4]);
+        float *o = a2 + (im.px2 + pm) * 32 + 4 * g;
+        *(f32x4 *)o = relu4(va);
+        *(f32x4 *)(o + 16) = relu4(vb);
     }
 }
 
-// Fused inference forward: one 256-thread block computes a 4 x 8 tile of
-// grid logits with every intermediate activation in LDS (level-3 input
-// 39 x 71, conv1 19 x 35 x 16, conv2 9 x 17 x 32; positions outside an
-// activation map are its zero padding).  Same helpers as the layer-by-layer
-// kernels, so the logits are bit-identical to cnn_forward's.
-constexpr int CF3H = 4, CF3W = 8;                         // grid positions per tile
-constexpr int CF2H = 2 * CF3H + 1, CF2W = 2 * CF3W + 1;   // conv2 window  9 x 17
-constexpr int CF1H = 2 * CF2H + 1, CF1W = 2 * CF2W + 1;   // conv1 window 19 x 35
-constexpr int CF0H = 2 * CF1H + 1, CF0W = 2 * CF1W + 1;   // input window 39 x 71
-constexpr int CF0S = CF0W + 1;                            // input row stride (u16)
-constexpr int CF0D = (CF0W + 1 + 3) / 4;                  // dwords per input row (18)
-constexpr int CF_LD = (CF0H * CF0D + 255) / 256;          // dword loads per thread (3)
-constexpr int CF1N = CF1H * CF1W, CF2N = CF2H * CF2W;
-constexpr int CF_U = CF2N * 32 > CF0H * CF0S ? CF2N * 32 : CF0H * CF0S;
+__global__ __launch_bounds__(256) void cnn_conv3_kernel(const CnnImg *__restrict__ imgs,
+                                                        const int32_t *__restrict__ pre_tiles, int n,
+                                                        int64_t total_tiles, const float *__restrict__ a2,
+                                                        float *__restrict__ a3, const uint16_t *__restrict__ wp3,
+                                                        const uint16_t *__restrict__ prm, float *__restrict__ z) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    if (tile >= total_tiles) return;
+    const int i = find_image(pre_tiles, n, tile);
+    const CnnImg im = imgs[i];
+    const int npx = im.w4 * im.h4;
+    const int m = lane & 15, g = lane >> 4;
+    const int pm = (int)(tile - pre_tiles[i]) * 16 + m;
+    const bool valid = pm < npx;
+    const int oy = valid ? pm / im.w4 : 0, ox = valid ? pm - oy * im.w4 : 0;
+    B3 b;
+#pragma unroll
+    for (int t = 0; t < 9; t++) {
+        float4 p, q;
+        load8(a2, 32, im.px2, im.w2, im.h2, 2 * oy + t / 3 - 1, 2 * ox + t % 3 - 1, 8 * g, valid, &p, &q);
+        split8(p, q, &b.h[t], &b.l[t]);
+    }
+    f32x4 v0, v1;
+    {
+        const W3 w = conv3_a(wp3, lane, 0);
+        v0 = relu4(conv3_mfma(w, b, conv_bias(prm, P_B3, lane)));
+    }
+    {
+        const W3 w = conv3_a(wp3, lane, 16);
+        v1 = relu4(conv3_mfma(w, b, conv_bias(prm, P_B3 + 16, lane)));
+    }
+    // head: block 0's sum plus block 1's, then the bias (fixed order)
+    const float part = head16(v0, prm, 0, lane) + head16(v1, prm, 16, lane);
+    if (valid) {
+        float *o = a3 + (im.px4 + pm) * 32 + 4 * g;
+        *(f32x4 *)o = v0;
+        *(f32x4 *)(o + 16) = v1;
+        if (g == 0) z[im.px4 + pm] = part + bf(prm[P_B4]);
+    }
+}
 
-__global__ __launch_bounds__(256) void cnn_fused_fwd_kernel(const CnnImg *__restrict__ imgs,
-                                                            const int32_t *__restrict__ pre_tiles, int n,
-                                                            const uint8_t *__restrict__ pyr,
-                                                            const uint16_t *__restrict__ prm,
-                                                            const uint16_t *__restrict__ wp2,
-                                                            const uint16_t *__restrict__ wp3, float *__restrict__ z) {
-    __shared__ __attribute__((aligned(16))) uint16_t s_a1[CF1N * 16];
-    __shared__ __attribute__((aligned(16))) uint16_t s_u[CF_U];     // input, then conv2 output
-    uint16_t *const s_c2 = s_u;
+// ---- fused inference forward: one 256-thread block computes a 4 x 8 tile
+// of grid logits with every activation in LDS.  Windows (rows x columns):
+// input 39 x 72 (global columns 8 X3 - 8 ..), conv1 19 x 35, conv2 9 x 17;
+// positions outside an activation map are its zero padding.
+constexpr int F3H = 4, F3W = 8;
+constexpr int F2H = 2 * F3H + 1, F2W = 2 * F3W + 1;      // 9 x 17
+constexpr int F1H = 2 * F2H + 1, F1W = 2 * F2W + 1;      // 19 x 35
+constexpr int F0H = 2 * F1H + 1, F0C = 2 * F1W + 2;      // 39 x 72
+constexpr int F0D = F0C / 4;                             // input dwords per row (18)
+constexpr int F1J = (F1W + 1) / 2, F2J = (F2W + 1) / 2;  // column pairs: 18, 9
+constexpr int A1P = F1H * F1J;                           // a1 entries per plane (342)
+constexpr int A2P = F2H * F2J;                           // a2 entries per plane (81)
+constexpr int A1N = 8 * A1P;                             // planes: 2 groups x (hi, lo) x 2 parities
+constexpr int A2N = 16 * A2P;                            // planes: 4 groups x (hi, lo) x 2 parities
+constexpr int F1N = F1H * F1W, F2N = F2H * F2W;          // 665, 153
+static_assert(F0H * F0C * 2 <= A2N * 16, "the staged input fits in the conv2 buffer");
+
+// 16-byte entry of 8 channels (group g, part h = 0 hi / 1 lo) of position
+// (r, c) in an even / odd column split layout with `planeN` entries per plane
+template <int P, int J>
+__device__ __forceinline__ int split_entry(int g, int h, int r, int c) {
+    return ((g * 2 + h) * 2 + (c & 1)) * P + r * J + (c >> 1);
+}
+
+__global__ __launch_bounds__(256, 2) void cnn_fused_fwd_kernel(const CnnImg *__restrict__ imgs,
+                                                               const int32_t *__restrict__ pre_tiles, int n,
+                                                               const uint8_t *__restrict__ pyr,
+                                                               const uint16_t *__restrict__ prm,
+                                                               const uint16_t *__restrict__ wp2,
+                                                               const uint16_t *__restrict__ wp3, float *__restrict__ z) {
+    __shared__ uint4 s_a1[A1N];
+    __shared__ uint4 s_u[A2N];               // staged input, then conv2's output
+    __shared__ float s_head[2][32];
+    uint32_t *const s_in = (uint32_t *)s_u;  // input as bf16 pairs, F0C / 2 dwords per row
+    uint2 *const s_a1h = (uint2 *)s_a1;
+    uint2 *const s_a2h = (uint2 *)s_u;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int m = lane & 15, grp = lane >> 4;
+    const int m = lane & 15, g = lane >> 4;
     const int bt = xcd_item(blockIdx.x, gridDim.x);
     const int i = find_image(pre_tiles, n, bt);
     const CnnImg im = imgs[i];
     const int lt = bt - pre_tiles[i];
-    const int ntx = (im.w4 + CF3W - 1) / CF3W;
-    const int Y3 = (lt / ntx) * CF3H, X3 = (lt % ntx) * CF3W;
-    const int Y2 = 2 * Y3 - 1, X2 = 2 * X3 - 1, Y1 = 2 * Y2 - 1, X1 = 2 * X2 - 1, Y0 = 2 * Y1 - 1, X0 = 2 * X1 - 1;
+    const int ntx = (im.w4 + F3W - 1) / F3W;
+    const int Y3 = (lt / ntx) * F3H, X3 = (lt % ntx) * F3W;
+    const int Y2 = 2 * Y3 - 1, X2 = 2 * X3 - 1, Y1 = 2 * Y2 - 1, X1 = 2 * X2 - 1, Y0 = 2 * Y1 - 1;
+    const int XS = 8 * X3 - 8;                // global column of staged column 0 (a multiple of 8)
 
-    // A. level-3 input window as bfloat16.  X0 - 1 = 8 X3 - 8 is a multiple
-    //    of 4 and rows start on 64-byte boundaries, so the window is read as
-    //    aligned dwords (bytes past the level width are masked); all loads
-    //    are issued before any is used.
+    // A. input window (I - 128) / 128 as bfloat16; rows start on 64-byte
+    //    boundaries and XS is a multiple of 4, so the window is read as
+    //    aligned dwords (bytes past the level width are zero padding)
     {
-        uint32_t v[CF_LD];
+        uint32_t v[3];
 #pragma unroll
-        for (int k = 0; k < CF_LD; k++) {
+        for (int k = 0; k < 3; k++) {
             const int d = tid + 256 * k;
-            const int rr = d / CF0D, j = d - rr * CF0D;
-            const int gy = Y0 + rr, gx = X0 - 1 + 4 * j;
-            const bool ok = d < CF0H * CF0D && gy >= 0 && gy < im.h3 && gx >= 0 && gx < im.w3;
+            const int rr = d / F0D, j = d - rr * F0D;
+            const int gy = Y0 + rr, gx = XS + 4 * j;
+            const bool ok = d < F0H * F0D && gy >= 0 && gy < im.h3 && gx >= 0 && gx < im.w3;
             v[k] = ok ? *(const uint32_t *)(pyr + im.lvl3 + (int64_t)gy * im.pitch3 + gx) : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < CF_LD; k++) {
+        for (int k = 0; k < 3; k++) {
             const int d = tid + 256 * k;
-            if (d >= CF0H * CF0D) continue;
-            const int rr = d / CF0D, j = d - rr * CF0D;
-            const int gy = Y0 + rr, gx = X0 - 1 + 4 * j;
-            const bool ok = gy >= 0 && gy < im.h3 && gx >= 0 && gx < im.w3;
+            if (d >= F0H * F0D) continue;
+            const int rr = d / F0D, j = d - rr * F0D;
+            const int gy = Y0 + rr, gx = XS + 4 * j;
+            const bool row_in = gy >= 0 && gy < im.h3 && gx >= 0;
+            float x[4];
 #pragma unroll
-            for (int bb = 0; bb < 4; bb++) {
-                const int cc = 4 * j - 1 + bb;                  // window column of byte bb
-                if (cc < 0 || cc >= CF0W) continue;
-                s_u[rr * CF0S + cc] = ok && gx + bb < im.w3 ? x_bf((int)((v[k] >> (8 * bb)) & 255u)) : (uint16_t)0;
-            }
+            for (int b = 0; b < 4; b++) x[b] = row_in && gx + b < im.w3 ? x_byte(v[k], b) : 0.f;
+            *(uint2 *)(s_in + rr * (F0C / 2) + 2 * j) = make_uint2(pk_bf(x[0], x[1]), pk_bf(x[2], x[3]));
         }
     }
     __syncthreads();
 
-    // B. conv1: one pixel per lane and M tile, 4 channels per lane
+    // B. conv1: one 16-pixel tile per MFMA; lane group g reads its tap row
+    //    (input columns 2 c - 2 .. 2 c + 1 of the window: two aligned dwords)
     {
-        const i16x4 w = conv1_weights(prm, lane);
-        float bias[4];
-#pragma unroll
-        for (int r = 0; r < 4; r++) bias[r] = bf(prm[P_B1 + 4 * grp + r]);
-        int toff[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int k = 4 * grp + j;
-            toff[j] = k < 9 ? (k / 3) * CF0S + (k % 3) : -1;
-        }
-        const int vy0 = max(0, -Y1), vy1 = min(CF1H, im.h1 - Y1), vx0 = max(0, -X1), vx1 = min(CF1W, im.w1 - X1);
-        for (int t = wave; t < (CF1N + 15) / 16; t += 4) {
+        const i16x4 w = conv1_a(prm, lane);
+        const f32x4 bias = conv_bias(prm, P_B1, lane);
+        const int ky = g < 3 ? g : 2;
+        const int vy0 = max(0, -Y1), vy1 = min(F1H, im.h1 - Y1), vx0 = max(0, -X1), vx1 = min(F1W, im.w1 - X1);
+        for (int t = wave; t < (F1N + 15) / 16; t += 4) {
             const int p = 16 * t + m;
-            const int r1 = p / CF1W, c1 = p - r1 * CF1W;
-            const int base = 2 * r1 * CF0S + 2 * c1;
-            i16x4 x;
-#pragma unroll
-            for (int j = 0; j < 4; j++) x[j] = (short)(p < CF1N && toff[j] >= 0 ? s_u[base + toff[j]] : 0);
-            const f32x4 acc = conv1_mfma(w, x);
-            if (p < CF1N) {
+            const int pp = p < F1N ? p : F1N - 1;
+            const int r1 = pp / F1W, c1 = pp - r1 * F1W;
+            const uint32_t *src = s_in + (2 * r1 + ky) * (F0C / 2) + c1;
+            const uint2 xb = make_uint2(src[0], src[1]);
+            f32x4 a = relu4(mfma16(w, as_i16x4(xb), bias));
+            if (p < F1N) {
                 const bool in = r1 >= vy0 && r1 < vy1 && c1 >= vx0 && c1 < vx1;
-                *(uint2 *)(s_a1 + p * 16 + 4 * grp) = in ? relu_pack4(acc, bias) : make_uint2(0, 0);
+                if (!in) a = splat4(0.f);
+                uint2 hi, lo;
+                split4(a, &hi, &lo);
+                s_a1h[2 * split_entry<A1P, F1J>(g >> 1, 0, r1, c1) + (g & 1)] = hi;
+                s_a1h[2 * split_entry<A1P, F1J>(g >> 1, 1, r1, c1) + (g & 1)] = lo;
             }
         }
     }
     __syncthreads();
 
-    // C. conv2 (16 -> 32)
+    // C. conv2 (16 -> 32): both 16-channel blocks per wave; per lane the
+    //    entry offsets of its K slices are fixed, the pixel adds a base
     {
-        uint4 w0[5], w1[5];
-        conv_weights<16>(wp2, lane, w0, w1);
-        float b0[4], b1[4];
+        const W2 wa = conv2_a(wp2, lane, 0), wb = conv2_a(wp2, lane, 16);
+        const f32x4 ba = conv_bias(prm, P_B2, lane), bb = conv_bias(prm, P_B2 + 16, lane);
+        int off[4];
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            b0[r] = bf(prm[P_B2 + 4 * grp + r]);
-            b1[r] = bf(prm[P_B2 + 16 + 4 * grp + r]);
+        for (int c = 0; c < 4; c++) {
+            const int t = 2 * c + (g >> 1), ky = t / 3, kx = t % 3;
+            off[c] = split_entry<A1P, F1J>(g & 1, 0, ky, kx);          // (r, c) = (ky, kx): parity kx & 1, pair kx >> 1
         }
-        const int vy0 = max(0, -Y2), vy1 = min(CF2H, im.h2 - Y2), vx0 = max(0, -X2), vx1 = min(CF2W, im.w2 - X2);
-        for (int t2 = wave; t2 < (CF2N + 15) / 16; t2 += 4) {
+        const int off8 = 2 * split_entry<A1P, F1J>(g >> 1, 0, 2, 2) + (g & 1);
+        const int vy0 = max(0, -Y2), vy1 = min(F2H, im.h2 - Y2), vx0 = max(0, -X2), vx1 = min(F2W, im.w2 - X2);
+        for (int t2 = wave; t2 < (F2N + 15) / 16; t2 += 4) {
             const int p = 16 * t2 + m;
-            const bool valid = p < CF2N;
-            const int r2 = valid ? p / CF2W : 0, c2 = valid ? p - r2 * CF2W : 0;
-            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+            const int pp = p < F2N ? p : F2N - 1;
+            const int r2 = pp / F2W, c2 = pp - r2 * F2W;
+            const int base = 2 * r2 * F1J + c2;                        // input (2 r2, 2 c2): row 2 r2, pair c2
+            B2 b;
 #pragma unroll
-            for (int c = 0; c < 5; c++) {
-                const int t = 2 * c + (grp >> 1), ci0 = 8 * (grp & 1);
-                uint4 xv = make_uint4(0, 0, 0, 0);
-                if (t < 9 && valid) xv = *(const uint4 *)(s_a1 + ((2 * r2 + t / 3) * CF1W + (2 * c2 + t % 3)) * 16 + ci0);
-                conv_mfma2(xv, w0[c], w1[c], acc0, acc1);
+            for (int c = 0; c < 4; c++) {
+                b.h[c] = s_a1[base + off[c]];
+                b.l[c] = s_a1[base + off[c] + 2 * A1P];
             }
-            if (valid) {
+            b.h8 = s_a1h[2 * base + off8];
+            b.l8 = s_a1h[2 * base + off8 + 4 * A1P];
+            f32x4 va, vb;
+            conv2_mfma(wa, wb, b, ba, bb, &va, &vb);
+            if (p < F2N) {
                 const bool in = r2 >= vy0 && r2 < vy1 && c2 >= vx0 && c2 < vx1;
-                *(uint2 *)(s_c2 + p * 32 + 4 * grp) = in ? relu_pack4(acc0, b0) : make_uint2(0, 0);
-                *(uint2 *)(s_c2 + p * 32 + 16 + 4 * grp) = in ? relu_pack4(acc1, b1) : make_uint2(0, 0);
+                va = in ? relu4(va) : splat4(0.f);
+                vb = in ? relu4(vb) : splat4(0.f);
+                uint2 hi, lo;
+                split4(va, &hi, &lo);
+                s_a2h[2 * split_entry<A2P, F2J>(g >> 1, 0, r2, c2) + (g & 1)] = hi;
+                s_a2h[2 * split_entry<A2P, F2J>(g >> 1, 1, r2, c2) + (g & 1)] = lo;
+                split4(vb, &hi, &lo);
+                s_a2h[2 * split_entry<A2P, F2J>(2 + (g >> 1), 0, r2, c2) + (g & 1)] = hi;
+                s_a2h[2 * split_entry<A2P, F2J>(2 + (g >> 1), 1, r2, c2) + (g & 1)] = lo;
             }
         }
     }
     __syncthreads();
 
-    // D. conv3 (32 -> 32) + 1x1 head: waves 0 and 1 take tile rows 2w, 2w + 1
-    if (wave < CF3H / 2) {
-        const int r3 = 2 * wave + (m >> 3), c3 = m & 7;
-        uint4 w0[9], w1[9];
-        conv_weights<32>(wp3, lane, w0, w1);
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    // D. conv3 (32 -> 32) + head: wave w takes 16 grid positions (w & 1) and
+    //    one 16-channel block (w >> 1); the two blocks' head sums meet in LDS
+    {
+        const int nt = wave & 1, mb = wave >> 1;
+        const int p = 16 * nt + m, r3 = p >> 3, c3 = p & 7;
+        const W3 w = conv3_a(wp3, lane, 16 * mb);
+        B3 b;
 #pragma unroll
         for (int t = 0; t < 9; t++) {
-            const uint4 xv = *(const uint4 *)(s_c2 + ((2 * r3 + t / 3) * CF2W + (2 * c3 + t % 3)) * 32 + 8 * grp);
-            conv_mfma2(xv, w0[t], w1[t], acc0, acc1);
+            const int e = split_entry<A2P, F2J>(g, 0, 2 * r3 + t / 3, 2 * c3 + t % 3);
+            b.h[t] = s_u[e];
+            b.l[t] = s_u[e + 2 * A2P];
         }
-        float b0[4], b1[4], h0[4], h1[4];
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            b0[r] = bf(prm[P_B3 + 4 * grp + r]);
-            b1[r] = bf(prm[P_B3 + 16 + 4 * grp + r]);
-            h0[r] = bf(prm[P_W4 + 4 * grp + r]);
-            h1[r] = bf(prm[P_W4 + 16 + 4 * grp + r]);
-        }
-        const float part = head_part(relu_pack4(acc0, b0), relu_pack4(acc1, b1), h0, h1);
+        const f32x4 v = relu4(conv3_mfma(w, b, conv_bias(prm, P_B3 + 16 * mb, lane)));
+        const float part = head16(v, prm, 16 * mb, lane);
+        if (g == 0) s_head[mb][p] = part;
+    }
+    __syncthreads();
+    if (tid < 32) {
+        const int r3 = tid >> 3, c3 = tid & 7;
         const int gy = Y3 + r3, gx = X3 + c3;
-        if (grp == 0 && gy < im.h4 && gx < im.w4) z[im.px4 + (int64_t)gy * im.w4 + gx] = part + bf(prm[P_B4]);
+        if (gy < im.h4 && gx < im.w4) z[im.px4 + (int64_t)gy * im.w4 + gx] = (s_head[0][tid] + s_head[1][tid]) + bf(prm[P_B4]);
     }
 }
 
@@ -438,7 +601,7 @@ __global__ void cnn_cells_kernel(const CnnImg *__restrict__ imgs, const int32_t 
 // g3 = dz w4 [a3 > 0].
 __global__ void cnn_head_bwd_kernel(int64_t total, const float *__restrict__ z, const float *__restrict__ target,
                                     float pos_weight, const uint16_t *__restrict__ prm,
-                                    const uint16_t *__restrict__ a3, float *__restrict__ dz, float *__restrict__ lz,
+                                    const float *__restrict__ a3, float *__restrict__ dz, float *__restrict__ lz,
                                     float *__restrict__ g3) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= total) return;
@@ -451,14 +614,14 @@ __global__ void cnn_head_bwd_kernel(int64_t total, const float *__restrict__ z, 
     const float d = (pos_weight * t * (s - 1.f) + (1.f - t) * s) * inv_n;
     dz[p] = d;
     for (int co = 0; co < 32; co++) {
-        const float a = bf(a3[p * 32 + co]);
+        const float a = a3[p * 32 + co];
         g3[p * 32 + co] = a > 0.f ? d * bf(prm[P_W4 + co]) : 0.f;
     }
 }
 
 // Partial sums of the head gradients over a pixel range.
 __global__ __launch_bounds__(256) void cnn_head_wgrad_kernel(int64_t total, const float *__restrict__ dz,
-                                                             const uint16_t *__restrict__ a3,
+                                                             const float *__restrict__ a3,
                                                              float *__restrict__ part) {
     __shared__ float s_acc[256][33];
     const int64_t chunk = (total + CNN_PARTS - 1) / CNN_PARTS;
@@ -467,7 +630,7 @@ __global__ __launch_bounds__(256) void cnn_head_wgrad_kernel(int64_t total, cons
     for (int k = 0; k < 33; k++) acc[k] = 0.f;
     for (int64_t p = lo + threadIdx.x; p < hi; p += 256) {
         const float d = dz[p];
-        for (int co = 0; co < 32; co++) acc[co] += d * bf(a3[p * 32 + co]);
+        for (int co = 0; co < 32; co++) acc[co] += d * a3[p * 32 + co];
         acc[32] += d;
     }
     for (int k = 0; k < 33; k++) s_acc[threadIdx.x][k] = acc[k];
@@ -485,7 +648,7 @@ __global__ __launch_bounds__(256) void cnn_head_wgrad_kernel(int64_t total, cons
 template <int CIN, int COUT, bool U8IN>
 __global__ __launch_bounds__(256) void cnn_wgrad_kernel(const CnnImg *__restrict__ imgs, const int32_t *__restrict__ pre_out,
                                                         int n, int64_t total, const float *__restrict__ g,
-                                                        const uint16_t *__restrict__ ain, const uint8_t *__restrict__ pyr,
+                                                        const float *__restrict__ ain, const uint8_t *__restrict__ pyr,
                                                         float *__restrict__ part, int w_at, int b_at) {
     constexpr int NW = COUT * 9 * CIN;
     constexpr int PER = NW < 256 * 9 ? (NW + 255) / 256 : 9;   // weights per thread (grid.y splits the rest)
@@ -521,7 +684,7 @@ __global__ __launch_bounds__(256) void cnn_wgrad_kernel(const CnnImg *__restrict
                 const int iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
                 if (iy >= 0 && iy < ih && ix >= 0 && ix < iw) {
                     if (U8IN) v = ((float)pyr[im.lvl3 + (int64_t)iy * im.pitch3 + ix] - 128.0f) * (1.0f / 128.0f);
-                    else v = bf(ain[(ib + (int64_t)iy * iw + ix) * CIN + ci]);
+                    else v = ain[(ib + (int64_t)iy * iw + ix) * CIN + ci];
                 }
             }
             s_a[pp][r] = v;
@@ -558,7 +721,7 @@ __global__ __launch_bounds__(256) void cnn_wgrad_kernel(const CnnImg *__restrict
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void cnn_dgrad_kernel(const CnnImg *__restrict__ imgs, const int32_t *__restrict__ pre_in,
                                                         int n, int64_t total_in, const float *__restrict__ gout,
-                                                        const uint16_t *__restrict__ ain, const uint16_t *__restrict__ prm,
+                                                        const float *__restrict__ ain, const uint16_t *__restrict__ prm,
                                                         int w_at, float *__restrict__ gin) {
     __shared__ float s_w[COUT * CIN * 9];
     for (int q = threadIdx.x; q < COUT * CIN * 9; q += 256) s_w[q] = bf(prm[w_at + q]);
@@ -573,7 +736,7 @@ __global__ __launch_bounds__(256) void cnn_dgrad_kernel(const CnnImg *__restrict
     const int64_t ib = CIN == 16 ? im.px1 : im.px2, ob = CIN == 16 ? im.px2 : im.px4;
     const int lq = (int)(q - ib), iy = lq / iw, ix = lq - iy * iw;
     float acc = 0.f;
-    if (bf(ain[q * CIN + ci]) > 0.f) {
+    if (ain[q * CIN + ci] > 0.f) {
         for (int ky = 0; ky < 3; ky++) {
             const int ty = iy + 1 - ky;
             if (ty & 1) continue;
@@ -634,8 +797,38 @@ __global__ void cnn_adam_kernel(float *__restrict__ w, uint16_t *__restrict__ wb
 // --------------------------------------------------------------- host side
 static int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
+// The proposer's device tables hold per-image prefix sums (pixels of each
+// layer, MFMA tiles, fused tiles, cells) as int32: a batch whose totals
+// reach 2^31 is refused (host only).
+int32_t cnn_plan_check(const vsfe_batch *b) {
+    if (b->info.n_levels < 4) return VSFE_OK;
+    int64_t s1 = 0, s2 = 0, s4 = 0, st1 = 0, st2 = 0, st4 = 0, sc = 0, stf = 0;
+    for (int i = 0; i < b->n_images; i++) {
+        const ImageDev &im = b->images[i];
+        const int64_t w3 = im.lv[3].w, h3 = im.lv[3].h;
+        const int64_t w1 = (w3 + 1) / 2, h1 = (h3 + 1) / 2, w2 = (w1 + 1) / 2, h2 = (h1 + 1) / 2;
+        const int64_t w4 = (w2 + 1) / 2, h4 = (h2 + 1) / 2;
+        s1 += w1 * h1;
+        s2 += w2 * h2;
+        s4 += w4 * h4;
+        st1 += (w1 * h1 + 15) / 16;
+        st2 += (w2 * h2 + 15) / 16;
+        st4 += (w4 * h4 + 15) / 16;
+        sc += (int64_t)im.lv[0].ncx * im.lv[0].ncy;
+        stf += ((w4 + F3W - 1) / F3W) * ((h4 + F3H - 1) / F3H);
+    }
+    const int64_t lim = (int64_t)1 << 31;
+    // the layer arrays are also indexed as (pixel * 32 + channel) in 64 bits;
+    // the counts themselves must stay below 2^31
+    if (s1 >= lim || s2 >= lim || s4 >= lim || st1 >= lim || st2 >= lim || st4 >= lim || sc >= lim || stf >= lim)
+        return fail(VSFE_ECAPACITY, "batch too large for the proposer's 32-bit prefix tables");
+    return VSFE_OK;
+}
+
 int32_t cnn_setup(vsfe_batch *b) {
     if (b->info.n_levels < 4) return VSFE_OK;            // no level 3: the proposer is unavailable
+    const int32_t rc = cnn_plan_check(b);
+    if (rc) return rc;
     CnnPlan *P = new CnnPlan();
     const int n = b->n_images;
     P->n = n;
@@ -680,7 +873,7 @@ int32_t cnn_setup(vsfe_batch *b) {
         st4 += ((int64_t)c.w4 * c.h4 + 15) / 16;
         sc += (int64_t)c.ncx0 * c.ncy0;
         st1 += ((int64_t)c.w1 * c.h1 + 15) / 16;
-        stf += (int64_t)((c.w4 + CF3W - 1) / CF3W) * ((c.h4 + CF3H - 1) / CF3H);
+        stf += (int64_t)((c.w4 + F3W - 1) / F3W) * ((c.h4 + F3H - 1) / F3H);
     }
     pre1[n] = (int32_t)s1;
     pre2[n] = (int32_t)s2;
@@ -706,11 +899,11 @@ int32_t cnn_setup(vsfe_batch *b) {
     P->off_wp3 = at;
     at = align256(at + 32 * 9 * 32 * 2);
     P->off_a1 = at;
-    at = align256(at + s1 * 16 * 2);
+    at = align256(at + s1 * 16 * 4);
     P->off_a2 = at;
-    at = align256(at + s2 * 32 * 2);
+    at = align256(at + s2 * 32 * 4);
     P->off_a3 = at;
-    at = align256(at + s4 * 32 * 2);
+    at = align256(at + s4 * 32 * 4);
     P->off_g1 = at;
     at = align256(at + s1 * 16 * 4);
     P->off_g2 = at;
@@ -763,17 +956,17 @@ static int32_t run_forward(const vsfe_batch *b, const CnnPlan *P, const uint8_t 
     const int n = P->n;
     const int32_t *pre = P->d_pre;
     uint16_t *wp2 = (uint16_t *)(ws + P->off_wp2), *wp3 = (uint16_t *)(ws + P->off_wp3);
-    uint16_t *a1 = (uint16_t *)(ws + P->off_a1), *a2 = (uint16_t *)(ws + P->off_a2), *a3 = (uint16_t *)(ws + P->off_a3);
+    float *a1 = (float *)(ws + P->off_a1), *a2 = (float *)(ws + P->off_a2), *a3 = (float *)(ws + P->off_a3);
     hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, prm, wp2, wp3);
     if (P->t1 > 0)
         hipLaunchKernelGGL(cnn_conv1_kernel, dim3((unsigned)((P->t1 + 3) / 4)), dim3(256), 0, st, P->d_img,
                            pre + 6 * (n + 1), n, P->t1, pyr, prm, a1);
     if (P->t2 > 0)
-        hipLaunchKernelGGL((cnn_conv_mfma_kernel<16, false>), dim3((unsigned)((P->t2 + 3) / 4)), dim3(256), 0, st,
-                           P->d_img, pre + 3 * (n + 1), n, P->t2, a1, a2, wp2, prm, (float *)nullptr);
+        hipLaunchKernelGGL(cnn_conv2_kernel, dim3((unsigned)((P->t2 + 3) / 4)), dim3(256), 0, st, P->d_img,
+                           pre + 3 * (n + 1), n, P->t2, a1, a2, wp2, prm);
     if (P->t4 > 0)
-        hipLaunchKernelGGL((cnn_conv_mfma_kernel<32, true>), dim3((unsigned)((P->t4 + 3) / 4)), dim3(256), 0, st,
-                           P->d_img, pre + 4 * (n + 1), n, P->t4, a2, a3, wp3, prm, z);
+        hipLaunchKernelGGL(cnn_conv3_kernel, dim3((unsigned)((P->t4 + 3) / 4)), dim3(256), 0, st, P->d_img,
+                           pre + 4 * (n + 1), n, P->t4, a2, a3, wp3, prm, z);
     (void)b;
     return check_launch("cnn forward");
 }
@@ -836,7 +1029,7 @@ int32_t cnn_backward(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *py
     uint8_t *ws = (uint8_t *)workspace;
     const int n = P->n;
     const int32_t *pre = P->d_pre;
-    uint16_t *a1 = (uint16_t *)(ws + P->off_a1), *a2 = (uint16_t *)(ws + P->off_a2), *a3 = (uint16_t *)(ws + P->off_a3);
+    float *a1 = (float *)(ws + P->off_a1), *a2 = (float *)(ws + P->off_a2), *a3 = (float *)(ws + P->off_a3);
     float *g1 = (float *)(ws + P->off_g1), *g2 = (float *)(ws + P->off_g2), *g3 = (float *)(ws + P->off_g3);
     float *dz = (float *)(ws + P->off_dz), *lz = (float *)(ws + P->off_lz), *part = (float *)(ws + P->off_part);
     if (P->px4 <= 0) return fail(VSFE_EINVAL, "empty proposer grid");

@@ -168,7 +168,9 @@ int32_t fail(int32_t code, const std::string &msg);
 int32_t check_launch(const char *what);
 int32_t check_common(const vsfe_ctx *ctx, const vsfe_batch *b, int32_t *status);
 
-// proposer geometry of a batch (no-op below 4 levels) and its release
+// proposer geometry of a batch (no-op below 4 levels) and its release;
+// cnn_plan_check: ECAPACITY when the proposer's 32-bit tables would overflow
+int32_t cnn_plan_check(const vsfe_batch *b);
 int32_t cnn_setup(vsfe_batch *b);
 void cnn_release(vsfe_batch *b);
 

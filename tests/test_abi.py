@@ -104,3 +104,17 @@ def test_detect_levels_rejects_null_arguments():
     lib = vsfe.lib()
     assert lib.fast_br_detect_levels(None, None, None, None, None, None, 0, 1, None, None) == vsfe.EINVAL
     assert b"null" in lib.vsfe_last_error()
+
+
+def test_batch_plan_refuses_proposer_overflow():
+    """A batch within the image count and size limits whose proposer tables
+    (32-bit prefix sums of conv1 pixels over the batch) would overflow is
+    refused at planning time with ECAPACITY, before anything is allocated."""
+    p = vsfe.make_params()
+    n, side = 400, 8192                       # 400 x 2371^2 conv1 pixels > 2^31
+    with pytest.raises(vsfe.VsfeError) as e:
+        vsfe.batch_plan(p, [side] * n, [side] * n, [side] * n, [i * side * side for i in range(n)])
+    assert e.value.code == vsfe.ECAPACITY
+    # the same images with 3 levels (no proposer) plan fine
+    info = vsfe.batch_plan(vsfe.make_params(n_levels=3), [side] * 2, [side] * 2, [side] * 2, [0, side * side])
+    assert info.n_images == 2
