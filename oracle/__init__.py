@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["pyramid.c", "fast.c", "detect.c", "orb.c", "stereo.c", "frontend.c"]
+SOURCES = ["pyramid.c", "fast.c", "detect.c", "orb.c", "stereo.c", "refine.c", "frontend.c"]
 
 
 def build(verbose: bool = False) -> str:
@@ -93,6 +93,7 @@ def _declare(L):
     L.or_describe.argtypes = [p, i32, i32, C.POINTER(OrParams), p, i32, C.POINTER(OrKps)]
     L.or_stereo.argtypes = [i32, C.POINTER(OrKps), i32, C.POINTER(OrKps), C.POINTER(OrParams),
                             p, p, p]
+    L.or_stereo_refine.argtypes = [p, p, i32, i32, i32, C.POINTER(OrKps), C.POINTER(OrKps), p, i32, i32, p, p]
     L.or_frontend_pair.argtypes = [p, p, i32, i32, C.POINTER(OrParams), p,
                                    C.POINTER(OrKps), pi, C.POINTER(OrKps), pi, p, p, p]
     L.or_frontend_pair.restype = i32
@@ -343,6 +344,28 @@ def stereo(kl: dict, kr: dict, params):
     lib().or_stereo(nl, C.byref(sl), nr, C.byref(sr), C.byref(pp), _ptr(idx), _ptr(dist),
                     _ptr(disp))
     return idx[:nl], dist[:nl], disp[:nl]
+
+
+def stereo_refine(pyr_l: np.ndarray, pyr_r: np.ndarray, W: int, H: int, kl: dict, kr: dict, idx,
+                  half_window=5, search_radius=5):
+    """Sub-pixel disparities (1/256 pixel, native scale; INT32_MIN = not
+    refined) and least SADs of the matches idx of a pair (packed pyramids)."""
+    nl, nr = len(kl["x"]), len(kr["x"])
+
+    def prep(k, n):
+        d = {f: np.ascontiguousarray(k[f]) if n else np.zeros(1, dtype=t) for f, t in KP_FIELDS}
+        d["desc"] = None
+        return d, _kps_struct(d, max(n, 1))
+
+    dl, sl = prep(kl, nl)
+    dr, sr = prep(kr, nr)
+    ix = np.ascontiguousarray(idx, dtype=np.int32) if nl else np.full(1, -1, np.int32)
+    disp = np.zeros(max(nl, 1), np.int32)
+    sad = np.zeros(max(nl, 1), np.uint32)
+    lib().or_stereo_refine(_ptr(np.ascontiguousarray(pyr_l, dtype=np.uint8)),
+                           _ptr(np.ascontiguousarray(pyr_r, dtype=np.uint8)), W, H, nl, C.byref(sl), C.byref(sr),
+                           _ptr(ix), half_window, search_radius, _ptr(disp), _ptr(sad))
+    return disp[:nl], sad[:nl]
 
 
 def frontend_image(img: np.ndarray, params, pattern=None, cell_mask0=None):

@@ -94,6 +94,14 @@ void    or_describe(const uint8_t *pyr, int32_t W, int32_t H, const or_params *p
 void    or_stereo(int32_t nl, const or_kps *L, int32_t nr, const or_kps *R,
                   const or_params *p, int32_t *idx, uint16_t *dist, int16_t *disp);
 
+/* Sub-pixel refinement of the stereo matches of one pair by SAD
+ * minimisation on the keypoints' levels (packed pyramids of both views);
+ * disp_q8: native-scale disparity in 1/256 pixel (INT32_MIN if not
+ * refined), sad_min: the least SAD (0xFFFFFFFF if not refined). */
+void    or_stereo_refine(const uint8_t *pyr_l, const uint8_t *pyr_r, int32_t W, int32_t H, int32_t nl,
+                         const or_kps *L, const or_kps *R, const int32_t *idx, int32_t w, int32_t r,
+                         int32_t *disp_q8, uint32_t *sad_min);
+
 /* Whole front-end for one stereo pair; returns 0 on success. */
 int32_t or_frontend_pair(const uint8_t *left, const uint8_t *right, int32_t W, int32_t H,
                          const or_params *p, const int8_t *pattern,
