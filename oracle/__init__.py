@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["pyramid.c", "fast.c", "detect.c", "orb.c", "stereo.c", "refine.c", "frontend.c"]
+SOURCES = ["pyramid.c", "fast.c", "detect.c", "orb.c", "stereo.c", "refine.c", "track.c", "frontend.c"]
 
 
 def build(verbose: bool = False) -> str:
@@ -94,6 +94,7 @@ def _declare(L):
     L.or_stereo.argtypes = [i32, C.POINTER(OrKps), i32, C.POINTER(OrKps), C.POINTER(OrParams),
                             p, p, p]
     L.or_stereo_refine.argtypes = [p, p, i32, i32, i32, C.POINTER(OrKps), C.POINTER(OrKps), p, i32, i32, p, p]
+    L.or_feature_match.argtypes = [i32, C.POINTER(OrKps), i32, C.POINTER(OrKps), i32, i32, i32, i32, p, p, p]
     L.or_frontend_pair.argtypes = [p, p, i32, i32, C.POINTER(OrParams), p,
                                    C.POINTER(OrKps), pi, C.POINTER(OrKps), pi, p, p, p]
     L.or_frontend_pair.restype = i32
@@ -366,6 +367,29 @@ def stereo_refine(pyr_l: np.ndarray, pyr_r: np.ndarray, W: int, H: int, kl: dict
                            _ptr(np.ascontiguousarray(pyr_r, dtype=np.uint8)), W, H, nl, C.byref(sl), C.byref(sr),
                            _ptr(ix), half_window, search_radius, _ptr(disp), _ptr(sad))
     return disp[:nl], sad[:nl]
+
+
+def feature_match(kq: dict, kr: dict, radius, level_band, match_th, ratio_pct):
+    """Matches of query keypoints kq against reference keypoints kr (dicts
+    with x0, y0, level, desc): (idx, best distance, runner-up distance)."""
+    nq, nr = len(kq["x0"]), len(kr["x0"])
+
+    def prep(k, n):
+        d = {}
+        for f, t in KP_FIELDS:
+            a = np.asarray(k[f], dtype=t) if (f in k and n) else np.zeros(max(n, 1), dtype=t)
+            d[f] = np.ascontiguousarray(a)
+        d["desc"] = np.ascontiguousarray(k["desc"], dtype=np.uint32) if n else np.zeros((1, 8), np.uint32)
+        return d, _kps_struct(d, max(n, 1))
+
+    dq, sq = prep(kq, nq)
+    dr, sr = prep(kr, nr)
+    idx = np.zeros(max(nq, 1), np.int32)
+    d1 = np.zeros(max(nq, 1), np.uint16)
+    d2 = np.zeros(max(nq, 1), np.uint16)
+    lib().or_feature_match(nq, C.byref(sq), nr, C.byref(sr), radius, level_band, match_th, ratio_pct, _ptr(idx),
+                           _ptr(d1), _ptr(d2))
+    return idx[:nq], d1[:nq], d2[:nq]
 
 
 def frontend_image(img: np.ndarray, params, pattern=None, cell_mask0=None):

@@ -102,6 +102,16 @@ void    or_stereo_refine(const uint8_t *pyr_l, const uint8_t *pyr_r, int32_t W, 
                          const or_kps *L, const or_kps *R, const int32_t *idx, int32_t w, int32_t r,
                          int32_t *disp_q8, uint32_t *sad_min);
 
+/* Descriptor matching of query keypoints against reference keypoints:
+ * candidates within `radius` native pixels (x and y) and `level_band`
+ * levels; least Hamming distance (ties: smaller index), runner-up distance;
+ * accepted if best <= match_th and (ratio_pct > 0 with a runner-up)
+ * 100 best < ratio_pct second.  idx -1 if not accepted; dist1 / dist2
+ * 0xFFFF when absent. */
+void    or_feature_match(int32_t nq, const or_kps *Q, int32_t nr, const or_kps *R, int32_t radius,
+                         int32_t level_band, int32_t match_th, int32_t ratio_pct, int32_t *idx,
+                         uint16_t *dist1, uint16_t *dist2);
+
 /* Whole front-end for one stereo pair; returns 0 on success. */
 int32_t or_frontend_pair(const uint8_t *left, const uint8_t *right, int32_t W, int32_t H,
                          const or_params *p, const int8_t *pattern,
