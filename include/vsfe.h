@@ -254,6 +254,21 @@ int32_t pyca_cull_aggregate(const vsfe_ctx *ctx, const vsfe_batch *b,
                             const vsfe_kp_soa *kps, int32_t *kp_count, int32_t *status,
                             void *stream);
 
+/* pyca_cull_aggregate for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same results, with the per-cell scratch taken from a fixed device
+ * array of the library (VSFE_NOALLOC_MAX_CELLS uint32 = 16 MiB per GPU,
+ * held until the process ends; its address is resolved at context
+ * creation) instead of a workspace argument.  Allocates nothing.  Every
+ * call on one GPU shares that array and leaves its contents behind (each
+ * call writes every rank it reads, nothing needs clearing): calls that
+ * overlap on one GPU, from any stream or context, race.  Errors: as
+ * pyca_cull_aggregate, plus ECAPACITY when the batch has more than
+ * VSFE_NOALLOC_MAX_CELLS cells. */
+#define VSFE_NOALLOC_MAX_CELLS (1 << 22)
+int32_t pyca_cull_aggregate_noalloc(const vsfe_ctx *ctx, const vsfe_batch *b, const uint32_t *cell_keys,
+                                    const vsfe_kp_soa *kps, int32_t *kp_count, int32_t *status, void *stream);
+
 /* Sec. III-2: intensity-centroid orientation over the radius-15 disc of the
  * unsmoothed level, quantised to 30 bins; 256 binary tests on the
  * bin-rotated pattern over the smoothed level.  Writes kps.bin and desc

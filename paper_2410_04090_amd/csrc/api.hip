@@ -325,6 +325,8 @@ int32_t vsfe_ctx_create(const vsfe_params *p, const int8_t *pattern, vsfe_ctx **
 
     rc = orb_prepare(dev);
     if (rc) return rc;
+    rc = pyca_prepare(dev);
+    if (rc) return rc;
     vsfe_ctx *c = new vsfe_ctx();
     c->p = *p;
     c->device = dev;

@@ -19,9 +19,34 @@
 //   order (level, cell row, cell column).
 #include <string.h>
 
+#include <mutex>
+
 #include "vsfe_internal.h"
 
 namespace vsfe {
+
+// Scratch of the allocation-free entry point pyca_cull_aggregate_noalloc:
+// one uint32 rank per cell, at most VSFE_NOALLOC_MAX_CELLS cells (16 MiB).
+// Each GPU the library runs on holds its own copy for the life of the
+// process.  In host code `scratch` names a host-side stand-in, never the
+// device array: its device address is looked up once per device
+// (pyca_prepare, at context creation) and only that address is passed on.
+static __device__ __align__(256) uint32_t scratch[VSFE_NOALLOC_MAX_CELLS];
+constexpr int SCRATCH_DEVICES = 64;
+static uint32_t *g_scratch_ptr[SCRATCH_DEVICES];
+static std::mutex g_scratch_mu;
+
+int32_t pyca_prepare(int device) {
+    if (device < 0 || device >= SCRATCH_DEVICES) return fail(VSFE_EUNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return VSFE_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(VSFE_EHIP, std::string("address of the aggregation scratch: ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = (uint32_t *)ptr;
+    return VSFE_OK;
+}
 
 // x * S approximates the native coordinate times 2^16 (x < 8192 / 1.2^l,
 // S < 65536 * 1.2^l + 1), so it stays below 2^29: a 24-bit multiply.
@@ -359,22 +384,13 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
     if (tid == 0) kp_count[blockIdx.x] = kept < n_max ? kept : n_max;
 }
 
-}  // namespace vsfe
-
-using namespace vsfe;
-
-extern "C" int32_t pyca_cull_aggregate(const vsfe_ctx *ctx, const vsfe_batch *b, const uint32_t *cell_keys,
-                                       void *workspace, const vsfe_kp_soa *kps, int32_t *kp_count,
-                                       int32_t *status, void *stream) {
-    int32_t rc = check_common(ctx, b, status);
-    if (rc) return rc;
-    if (!cell_keys || !workspace || !kps || !kp_count) return fail(VSFE_EINVAL, "null buffer");
-    if (!kps->x || !kps->y || !kps->level || !kps->flags || !kps->score || !kps->x0 || !kps->y0 || !kps->kl ||
-        !kps->kr || !kps->bin)
-        return fail(VSFE_EINVAL, "null keypoint array");
+// Aggregation and cap with `rank` (one uint32 per cell of the batch) as
+// the scratch: every cell's rank is written before it is read, so the
+// scratch needs no clearing.
+static int32_t pyca_run(const vsfe_ctx *ctx, const vsfe_batch *b, const uint32_t *cell_keys, uint32_t *rank,
+                        const vsfe_kp_soa *kps, int32_t *kp_count, int32_t *status, hipStream_t st) {
+    int32_t rc = VSFE_OK;
     const vsfe_params &p = ctx->p;
-    hipStream_t st = (hipStream_t)stream;
-    uint32_t *rank = (uint32_t *)workspace;
     PfaLevelTab tab;
     memset(&tab, 0, sizeof(tab));
     for (int l = 0; l < p.n_levels; l++) {
@@ -410,4 +426,42 @@ extern "C" int32_t pyca_cull_aggregate(const vsfe_ctx *ctx, const vsfe_batch *b,
     hipLaunchKernelGGL(select_compact_kernel, dim3(b->n_images), dim3(SEL_THREADS), 0, st, b->d_images, cell_keys,
                        rank, *kps, kp_count, p.n_max, status, tab);
     return check_launch("pyca_cull_aggregate (select)");
+}
+
+static int32_t pyca_args(const vsfe_ctx *ctx, const vsfe_batch *b, const uint32_t *cell_keys, const vsfe_kp_soa *kps,
+                         int32_t *kp_count, int32_t *status) {
+    int32_t rc = check_common(ctx, b, status);
+    if (rc) return rc;
+    if (!cell_keys || !kps || !kp_count) return fail(VSFE_EINVAL, "null buffer");
+    if (!kps->x || !kps->y || !kps->level || !kps->flags || !kps->score || !kps->x0 || !kps->y0 || !kps->kl ||
+        !kps->kr || !kps->bin)
+        return fail(VSFE_EINVAL, "null keypoint array");
+    return VSFE_OK;
+}
+
+}  // namespace vsfe
+
+using namespace vsfe;
+
+extern "C" int32_t pyca_cull_aggregate(const vsfe_ctx *ctx, const vsfe_batch *b, const uint32_t *cell_keys,
+                                       void *workspace, const vsfe_kp_soa *kps, int32_t *kp_count,
+                                       int32_t *status, void *stream) {
+    const int32_t rc = pyca_args(ctx, b, cell_keys, kps, kp_count, status);
+    if (rc) return rc;
+    if (!workspace) return fail(VSFE_EINVAL, "null workspace");
+    return pyca_run(ctx, b, cell_keys, (uint32_t *)workspace, kps, kp_count, status, (hipStream_t)stream);
+}
+
+extern "C" int32_t pyca_cull_aggregate_noalloc(const vsfe_ctx *ctx, const vsfe_batch *b, const uint32_t *cell_keys,
+                                               const vsfe_kp_soa *kps, int32_t *kp_count, int32_t *status,
+                                               void *stream) {
+    const int32_t rc = pyca_args(ctx, b, cell_keys, kps, kp_count, status);
+    if (rc) return rc;
+    if (b->info.n_cells > VSFE_NOALLOC_MAX_CELLS)
+        return fail(VSFE_ECAPACITY, "batch has " + std::to_string(b->info.n_cells) +
+                                        " cells; the allocation-free aggregation holds at most " +
+                                        std::to_string((long long)VSFE_NOALLOC_MAX_CELLS));
+    uint32_t *ptr = (ctx->device >= 0 && ctx->device < SCRATCH_DEVICES) ? g_scratch_ptr[ctx->device] : nullptr;
+    if (!ptr) return fail(VSFE_EUNSUPPORTED, "aggregation scratch not prepared on this device");
+    return pyca_run(ctx, b, cell_keys, ptr, kps, kp_count, status, (hipStream_t)stream);
 }

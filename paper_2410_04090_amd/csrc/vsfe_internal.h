@@ -185,6 +185,8 @@ int32_t detect_launch(const vsfe_ctx *ctx, const vsfe_batch *b, const DetItem *i
 
 // one-time upload of the orientation disc tables to the current device
 int32_t orb_prepare(int device);
+// one-time lookup of the aggregation scratch's address on the current device
+int32_t pyca_prepare(int device);
 
 // level geometry shared by the host planner
 void level_size(int32_t W, int32_t H, int32_t l, int32_t *Wl, int32_t *Hl);

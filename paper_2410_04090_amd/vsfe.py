@@ -79,7 +79,9 @@ EXPORTS = ["vsfe_params_default", "vsfe_params_check", "vsfe_level_geometry", "v
            "vsfe_batch_info_get", "vsfe_batch_level_info", "vsfe_ctx_set_tile", "vsfe_last_error",
            "pyramid_build", "fast_br_detect", "fast_br_detect_levels", "pyca_cull_aggregate", "orb_describe",
            "stereo_match", "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step",
-           "vsfe_batch_tiles_get", "vsfe_batch_set_tiles", "vsfe_batch_autotune"]
+           "vsfe_batch_tiles_get", "vsfe_batch_set_tiles", "vsfe_batch_autotune", "pyca_cull_aggregate_noalloc"]
+
+NOALLOC_MAX_CELLS = 1 << 22
 
 _lib = None
 
@@ -128,6 +130,7 @@ def lib():
     L.fast_br_detect.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.fast_br_detect_levels.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, vp]
     L.pyca_cull_aggregate.argtypes = [vp, vp, vp, vp, C.POINTER(KpSoa), vp, vp, vp]
+    L.pyca_cull_aggregate_noalloc.argtypes = [vp, vp, vp, C.POINTER(KpSoa), vp, vp, vp]
     L.orb_describe.argtypes = [vp, vp, vp, vp, C.POINTER(KpSoa), vp, vp, vp, vp]
     L.stereo_match.argtypes = [vp, vp, C.POINTER(KpSoa), vp, vp, vp, vp, vp, vp, vp]
     L.vsfe_cnn_info_get.argtypes = [vp, C.POINTER(CnnInfo)]
@@ -135,7 +138,8 @@ def lib():
     L.cnn_propose.argtypes = [vp, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp]
     L.cnn_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_float, vp, vp, vp, vp]
     L.cnn_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]
-    for f in ("pyramid_build", "fast_br_detect", "fast_br_detect_levels", "pyca_cull_aggregate", "orb_describe",
+    for f in ("pyramid_build", "fast_br_detect", "fast_br_detect_levels", "pyca_cull_aggregate",
+              "pyca_cull_aggregate_noalloc", "orb_describe",
               "stereo_match", "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step"):
         getattr(L, f).restype = i32
     _lib = L
@@ -281,6 +285,12 @@ def pyca_cull_aggregate(ctx, b, cell_keys, workspace, kps, kp_count, status, str
     s = kp_soa(kps)
     _check(lib().pyca_cull_aggregate(ctx, b, _p(cell_keys), _p(workspace), C.byref(s), _p(kp_count),
                                      _p(status), _stream(stream)))
+
+
+def pyca_cull_aggregate_noalloc(ctx, b, cell_keys, kps, kp_count, status, stream=None):
+    s = kp_soa(kps)
+    _check(lib().pyca_cull_aggregate_noalloc(ctx, b, _p(cell_keys), C.byref(s), _p(kp_count), _p(status),
+                                             _stream(stream)))
 
 
 def orb_describe(ctx, b, images, pyr, kps, kp_count, desc, status, stream=None):
