@@ -106,6 +106,34 @@ def stored_traffic(call, workload):
         return None
 
 
+def stored_counters(call, workload):
+    """SQ instruction counts per launch of `call` from the committed counter
+    summary (profiles/<call>_<workload>_sq.txt), or None when there is none
+    or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_sq.txt" % (call, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_sha(call):
+        return None
+    try:
+        return {k: float(kv[k]) for k in ("insts_valu_per_launch", "insts_salu_per_launch", "insts_lds_per_launch")}
+    except (KeyError, ValueError):
+        return None
+
+
+# VALU issue peak: one wave64 instruction per SIMD every 4 cycles (16 lanes
+# per SIMD), 4 SIMDs per CU, 256 CUs at 2.4 GHz: 256 x 4 x 2.4e9 / 4 =
+# 614 G wave-instructions/s = 39.3 T lane-operations/s
+VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
+VALU_LANE_OPS_PEAK_T = VALU_WAVE_INSTS_PER_S * 64 / 1e12
+
+
 def copy_probe(mib):
     """A plain device-to-device copy of known size, for scaling the HBM
     byte counters (run under the counter profiler)."""
@@ -237,6 +265,70 @@ def learned_path(args, fe, sizes, stream, exact_value):
             "thresh": tau, "weights": os.path.relpath(path, ROOT), "calls_us": call_us}
 
 
+def middle_end(args, fe, stream):
+    """Per-call times of the middle-end steps after stereo matching: sub-pixel
+    refinement of the matches, and descriptor matching of every image's
+    keypoints against a reference set (here the image's own keypoints, whose
+    windows hold the same candidates a previous frame's would)."""
+    import torch
+    from paper_2410_04090_amd import vsfe
+    c, b = fe.ctx, fe.batch
+    fe.refine(stream=stream)
+    torch.cuda.synchronize()
+    n_left = int(sum(fe.kp_count[0::2].tolist()))
+    refined = sum(int((fe.refined(p)[0] != -(2 ** 31)).sum()) for p in range(fe.n // 2))
+    ws = torch.zeros(max(vsfe.feature_match_workspace(b), 4), dtype=torch.uint8, device="cuda")
+    cap = int(fe.info.kp_capacity)
+    idx = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    d1 = torch.zeros(cap, dtype=torch.int16, device="cuda")
+    d2 = torch.zeros(cap, dtype=torch.int16, device="cuda")
+    calls = {
+        "stereo_refine": lambda: fe.refine(stream=stream),
+        "feature_match": lambda: vsfe.feature_match(c, b, fe.kps, fe.kp_count, fe.desc, fe.kps, fe.kp_count, fe.desc,
+                                                    16, 1, 64, 90, ws, idx, d1, d2, fe.status, stream),
+    }
+    out = {k: round(time_call(f, args.kernel_reps, stream), 2) for k, f in calls.items()}
+    return {"calls_us": out, "refined_frac": round(refined / max(n_left, 1), 4),
+            "refine_window": 2 * fe.REFINE_HALF_WINDOW + 1, "refine_radius": fe.REFINE_RADIUS,
+            "feature_match": {"radius": 16, "level_band": 1, "match_th": 64, "ratio_pct": 90}}
+
+
+def culling_ablation(args, wl, fe, stream):
+    """Feature Culling over a materialised response matrix with the paper's
+    thread schemes (MLPT + TEWA, log2 reduction, MLPT with one block per
+    cell) against the fused culling of the detector: per level of this
+    batch at its cell sizes, and at level 0 with the paper's cell sizes."""
+    import torch
+    from paper_2410_04090_amd import vsfe
+    c, b = fe.ctx, fe.batch
+    crf = torch.zeros(max(int(fe.info.crf_elems), 1), dtype=torch.int16, device="cuda")
+    keys = torch.zeros(max(int(fe.info.n_cells), 1) * 16, dtype=torch.int32, device="cuda")
+    fused = time_call(lambda: vsfe.fast_br_detect(c, b, fe.images, fe.pyr, None, fe.cell_keys, None, fe.status,
+                                                  stream), args.kernel_reps, stream)
+    dump = time_call(lambda: vsfe.fast_br_detect(c, b, fe.images, fe.pyr, None, fe.cell_keys, crf, fe.status,
+                                                 stream), args.kernel_reps, stream)
+    schemes = {"mlpt_tewa": 0, "log2_block_per_cell": 1, "mlpt_block_per_cell": 2}
+    per_level = []
+    for lv in range(wl.params.n_levels):
+        cell = int(fe.level_info(0, lv).cell)
+        n_loc = max(1, -(-cell // 8))
+        row = {"level": lv, "cell": cell}
+        for name, sc in schemes.items():
+            row[name] = round(time_call(lambda: vsfe.fc_cull_crf(c, b, crf, lv, cell, sc, n_loc, keys, fe.status,
+                                                                 stream), args.kernel_reps, stream), 2)
+        per_level.append(row)
+    sweep = []
+    for cell in (23, 17, 13, 7, 3):
+        n_loc = max(1, -(-cell // 8))
+        row = {"cell": cell}
+        for name, sc in schemes.items():
+            row[name] = round(time_call(lambda: vsfe.fc_cull_crf(c, b, crf, 0, cell, sc, n_loc, keys, fe.status,
+                                                                 stream), args.kernel_reps, stream), 2)
+        sweep.append(row)
+    return {"fused_detect_us": round(fused, 2), "detect_with_dump_us": round(dump, 2), "per_level_us": per_level,
+            "level0_cell_sweep_us": sweep, "images": fe.n}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +343,8 @@ def main():
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the middle-end calls, the culling ablation and the repeatability harness")
     ap.add_argument("--proposer", default=None, help="proposer weights (default: the packaged ones for the image size)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
@@ -358,10 +452,24 @@ def main():
     dominant = max(call_us, key=call_us.get)
     ach = alg[dominant] / (call_us[dominant] * 1e-6) / 1e9
     traffic = stored_traffic(dominant, args.workload)
-    roof = {"kernel": dominant, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "alg_bytes_per_launch": int(alg[dominant]), "avg_launch_us": round(call_us[dominant], 2),
-            "source_sha": source_sha(dominant)}
+    hbm = {"achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+           "traffic": traffic, "alg_bytes_per_launch": int(alg[dominant])}
+    sq = stored_counters(dominant, args.workload)
+    valu = None
+    if sq is not None:
+        # issued VALU instructions over the launch against the issue peak
+        issue = sq["insts_valu_per_launch"] / (call_us[dominant] * 1e-6) / VALU_WAVE_INSTS_PER_S
+        valu = {"achieved": round(sq["insts_valu_per_launch"] * 64 / (call_us[dominant] * 1e-6) / 1e12, 2),
+                "peak": round(VALU_LANE_OPS_PEAK_T, 1), "unit": "T lane-ops/s (issued int32 VALU)",
+                "frac": round(issue, 4), "insts_valu_per_launch": sq["insts_valu_per_launch"],
+                "insts_salu_per_launch": sq["insts_salu_per_launch"]}
+    if valu is not None and valu["frac"] > hbm["frac"]:
+        roof = {"kernel": dominant, "bound": "alu", "achieved": valu["achieved"], "peak": valu["peak"],
+                "unit": valu["unit"], "frac": valu["frac"], "traffic": traffic, "hbm": hbm, "valu": valu}
+    else:
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm["frac"], "traffic": traffic, "hbm": hbm, "valu": valu}
+    roof.update({"avg_launch_us": round(call_us[dominant], 2), "source_sha": source_sha(dominant)})
     # whole-path algorithmic bytes: level 0 read once, every other level
     # written once and read once, keypoints (16 B) and descriptors (32 B)
     # written, matches (8 B per left keypoint) written
@@ -383,10 +491,23 @@ def main():
     }
     if tune is not None:
         res["autotune"] = tune
+    if not args.no_extras and fe.stereo:
+        res["middle_end"] = middle_end(args, fe, stream)
     learned = None if args.no_learned else learned_path(args, fe, sizes, stream, value)
     if learned is not None:
         res["learned"] = learned
+    if not args.no_extras:
+        res["culling_ablation"] = culling_ablation(args, wl, fe, stream)
     fe.close()
+    if not args.no_extras:
+        from paper_2410_04090_amd import repeatability
+        t_rep = time.perf_counter()
+        rep = repeatability.run()
+        res["repeatability"] = {"mean_f1": {k: round(v, 4) for k, v in rep["mean_f1"].items()},
+                                "f1_per_angle": {str(a): {k: round(v["f1"], 4) for k, v in rep["per_angle"][a].items()}
+                                                 for a in rep["per_angle"]},
+                                "scenes": rep["scenes"], "size": rep["size"], "eps": rep["eps"],
+                                "tol_px": rep["tol_px"], "seconds": round(time.perf_counter() - t_rep, 1)}
     if cpu is not None:
         res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)

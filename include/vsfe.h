@@ -13,6 +13,12 @@
  *   orb_describe         smoothing, ORB orientation, rBRIEF (Sec. III-2)
  *   stereo_match         descriptor-distance stereo matching along
  *                        rectified rows (Sec. III-3, middle-end)
+ *   stereo_refine        sub-pixel refinement of the matches by correlation
+ *                        (SAD) minimisation (Sec. III-3, middle-end)
+ *   feature_match        descriptor matching against the previous frame or
+ *                        projected map points (Sec. III-3, middle-end)
+ *   fc_cull_crf          Feature Culling over a materialised response matrix
+ *                        with the paper's thread schemes (ablation)
  *   cnn_*                learned cell proposer gating the detector
  *
  * Conventions (all calls):
@@ -215,6 +221,14 @@ const char *vsfe_last_error(void);
 int32_t pyramid_build(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
                       uint8_t *pyr, int32_t *status, void *stream);
 
+/* pyramid_build restricted to levels level_begin <= l < level_end
+ * (1 <= level_begin): each from level l - 1, which must already be built.
+ * Lets later levels be built on a second stream while an earlier level is
+ * consumed (the learned proposer needs levels 1..3 only).  Errors: EINVAL
+ * (null buffers, an empty or out-of-range level range), EHIP. */
+int32_t pyramid_build_levels(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images, uint8_t *pyr,
+                             int32_t level_begin, int32_t level_end, int32_t *status, void *stream);
+
 /* Sec. II-A Eq. 1-3, Sec. III-1 and Sec. II-C-1: for every pixel inside the
  * border of every level, FAST labels at eps_hi (and eps_lo), the longest
  * cyclic bright / dark run N, the Bounded-Rectification test
@@ -224,7 +238,8 @@ int32_t pyramid_build(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *i
  * no eps_hi corner.  cell_keys (n_cells, written, 0 = empty).
  * cell_mask (n_cells0 bytes, nullable): learned gating, a level-l cell runs
  * only if its native-scale footprint overlaps a non-zero level-0 cell; the
- * keys of other cells are 0.
+ * keys of other cells are 0.  The gated launch visits only the tiles with a
+ * running cell (a device-built work list; the others cost one early exit).
  * crf_debug (crf_elems, nullable): per-pixel eps_hi response, 0 elsewhere
  * (and 0 in cells that a cell_mask skips). */
 int32_t fast_br_detect(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
@@ -288,6 +303,71 @@ int32_t orb_describe(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *im
 int32_t stereo_match(const vsfe_ctx *ctx, const vsfe_batch *b, const vsfe_kp_soa *kps,
                      const int32_t *kp_count, const uint32_t *desc, int32_t *match_idx,
                      uint16_t *match_dist, int16_t *match_disp, int32_t *status, void *stream);
+
+/* Sec. III-3 (the middle-end's stereo matcher pairs correlation
+ * minimisation with descriptor-distance minimisation): sub-pixel refinement
+ * of the stereo matches.  For each left keypoint slot i < kp_count of pair p
+ * with match_idx[p * n_max + i] = j >= 0 (as written by stereo_match): on
+ * the keypoint's level of both views (unsmoothed), SAD(s) of the
+ * (2 half_window + 1)^2 window around the left keypoint against the window
+ * around the right keypoint's column shifted by s in [-search_radius,
+ * search_radius], same rows; s* = least SAD (ties: smaller |s|, then smaller
+ * s); the vertex of the parabola through SAD(s* - 1), SAD(s*), SAD(s* + 1),
+ * offset (S- - S+) / (2 (S- - 2 S0 + S+)) in 1/256 pixel rounded half away
+ * from zero (0 if the denominator is 0).  Outputs (match_capacity entries,
+ * same slots as stereo_match; entries of slots >= kp_count untouched):
+ * disp_q8 = native-scale disparity in 1/256 pixel,
+ * floor(((256 x_l - (256 (x_r + s*) + offset)) S_l + 2^15) / 2^16),
+ * INT32_MIN when not refined (no match, a window leaving the level, or
+ * s* = +-search_radius); sad_min (nullable) = SAD(s*), 0xFFFFFFFF when not
+ * refined.  EINVAL: half_window or search_radius outside 1..7, an odd image
+ * count or a pair of unequal sizes, null buffers. */
+int32_t stereo_refine(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images, const uint8_t *pyr,
+                      const vsfe_kp_soa *kps, const int32_t *kp_count, const int32_t *match_idx,
+                      int32_t half_window, int32_t search_radius, int32_t *disp_q8, uint32_t *sad_min,
+                      int32_t *status, void *stream);
+
+/* Sec. III-3 (the middle-end's "Descriptor Matching" beside "Conic
+ * Projections", Fig. "slampipeline"): match the keypoints of a frame (the
+ * query: image i's slots [i n_max, i n_max + query_count[i]) of `query`,
+ * descriptors query_desc) against reference keypoints laid out the same way
+ * (the previous frame's results, or map points whose x0 / y0 hold their
+ * predicted native-scale positions and level their predicted level).  A
+ * reference is a candidate when |x0_q - x0_r| <= radius, |y0_q - y0_r| <=
+ * radius (native pixels) and |level_q - level_r| <= level_band; best = least
+ * Hamming distance (ties: smaller reference index), second = least distance
+ * among the other candidates; accepted when best <= match_th and, with
+ * ratio_pct > 0 and a second candidate, 100 best < ratio_pct second.
+ * Outputs per query slot (kp_capacity entries): match_idx (reference index
+ * within the image, -1 if not accepted), dist1 / dist2 (0xFFFF if absent).
+ * workspace: vsfe_feature_match_workspace() bytes of device scratch
+ * (overwritten).  EINVAL: radius outside 0..255, level_band outside 0..11,
+ * match_th outside 0..256, ratio_pct outside 0..100, null buffers. */
+int32_t vsfe_feature_match_workspace(const vsfe_batch *b, int64_t *bytes);
+int32_t feature_match(const vsfe_ctx *ctx, const vsfe_batch *b, const vsfe_kp_soa *query,
+                      const int32_t *query_count, const uint32_t *query_desc, const vsfe_kp_soa *ref,
+                      const int32_t *ref_count, const uint32_t *ref_desc, int32_t radius, int32_t level_band,
+                      int32_t match_th, int32_t ratio_pct, void *workspace, int32_t *match_idx, uint16_t *dist1,
+                      uint16_t *dist2, int32_t *status, void *stream);
+
+/* Sec. II-C-1 as the paper schedules it, kept as an ablation beside the
+ * fused culling of fast_br_detect: Feature Culling over a materialised
+ * response matrix `crf` (the crf_debug output of fast_br_detect) of one
+ * pyramid level of every image, with square cells of side `cell` (1..32):
+ * per cell the largest key (response << 10) | (1023 - offset in cell),
+ * 0 = no corner (the keys of fast_br_detect without a fallback threshold).
+ * scheme 0: multi-location-per-thread culling (ceil(cell / n_loc) threads
+ * per column, n_loc rows each, then the column maxima at a stride) with
+ * thread-efficient warp allocation (128-thread-wide blocks packing
+ * floor(128 / cell) cells); scheme 1: log2 tree reduction, one block and
+ * one thread per pixel of a cell; scheme 2: scheme 0 with one block per
+ * cell.  keys: image i's cells row-major from i * stride
+ * (vsfe_fc_cull_stride).  EINVAL: level out of range, cell outside 1..32,
+ * scheme outside 0..2, n_loc outside 1..32 or ceil(cell / n_loc) > 8
+ * (schemes 0 and 2). */
+int32_t vsfe_fc_cull_stride(const vsfe_batch *b, int32_t level, int32_t cell, int64_t *stride);
+int32_t fc_cull_crf(const vsfe_ctx *ctx, const vsfe_batch *b, const uint16_t *crf, int32_t level, int32_t cell,
+                    int32_t scheme, int32_t n_loc, uint32_t *keys, int32_t *status, void *stream);
 
 /* ---------------------------------------------------- learned cell proposer
  *

@@ -395,6 +395,7 @@ int32_t vsfe_batch_destroy(vsfe_batch *b) {
     if (b->d_det_items) (void)hipFree(b->d_det_items);
     if (b->d_chunks) (void)hipFree(b->d_chunks);
     if (b->d_run) (void)hipFree(b->d_run);
+    if (b->d_item_list) (void)hipFree(b->d_item_list);
     if (b->d_row_tab) (void)hipFree(b->d_row_tab);
     cnn_release(b);
     delete b;
@@ -428,6 +429,7 @@ int32_t vsfe_batch_create(const vsfe_ctx *ctx, int32_t n, const int32_t *widths,
     if (!rc) rc = upload(b->h_chunks, &b->d_chunks);
     if (!rc && b->info.n_cells > 0 && hipMalloc((void **)&b->d_run, (size_t)b->info.n_cells) != hipSuccess)
         rc = fail(VSFE_EHIP, "hipMalloc of the run-flag table failed");
+    if (!rc) rc = det_list_alloc(b);
     if (!rc && b->n_row_tab > 0 &&
         hipMalloc((void **)&b->d_row_tab, (size_t)b->n_row_tab * sizeof(int32_t)) != hipSuccess)
         rc = fail(VSFE_EHIP, "hipMalloc of the row-start table failed");

@@ -415,6 +415,11 @@ constexpr int A1N = 8 * A1P;                             // planes: 2 groups x (
 constexpr int A2N = 16 * A2P;                            // planes: 4 groups x (hi, lo) x 2 parities
 constexpr int F1N = F1H * F1W, F2N = F2H * F2W;          // 665, 153
 static_assert(F0H * F0C * 2 <= A2N * 16, "the staged input fits in the conv2 buffer");
+// 8 waves per block: with two blocks per CU (LDS) that is four waves per
+// SIMD, enough to overlap one block's barriers and loads with the other's
+// matrix work
+constexpr int F_WAVES = 8, F_THREADS = 64 * F_WAVES;
+constexpr int F_LD = (F0H * F0D + F_THREADS - 1) / F_THREADS;   // input dwords per thread (2)
 
 // 16-byte entry of 8 channels (group g, part h = 0 hi / 1 lo) of position
 // (r, c) in an even / odd column split layout with `planeN` entries per plane
@@ -423,7 +428,7 @@ __device__ __forceinline__ int split_entry(int g, int h, int r, int c) {
     return ((g * 2 + h) * 2 + (c & 1)) * P + r * J + (c >> 1);
 }
 
-__global__ __launch_bounds__(256, 2) void cnn_fused_fwd_kernel(const CnnImg *__restrict__ imgs,
+__global__ __launch_bounds__(F_THREADS, 2) void cnn_fused_fwd_kernel(const CnnImg *__restrict__ imgs,
                                                                const int32_t *__restrict__ pre_tiles, int n,
                                                                const uint8_t *__restrict__ pyr,
                                                                const uint16_t *__restrict__ prm,
@@ -450,18 +455,18 @@ __global__ __launch_bounds__(256, 2) void cnn_fused_fwd_kernel(const CnnImg *__r
     //    boundaries and XS is a multiple of 4, so the window is read as
     //    aligned dwords (bytes past the level width are zero padding)
     {
-        uint32_t v[3];
+        uint32_t v[F_LD];
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const int d = tid + 256 * k;
+        for (int k = 0; k < F_LD; k++) {
+            const int d = tid + F_THREADS * k;
             const int rr = d / F0D, j = d - rr * F0D;
             const int gy = Y0 + rr, gx = XS + 4 * j;
             const bool ok = d < F0H * F0D && gy >= 0 && gy < im.h3 && gx >= 0 && gx < im.w3;
             v[k] = ok ? *(const uint32_t *)(pyr + im.lvl3 + (int64_t)gy * im.pitch3 + gx) : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const int d = tid + 256 * k;
+        for (int k = 0; k < F_LD; k++) {
+            const int d = tid + F_THREADS * k;
             if (d >= F0H * F0D) continue;
             const int rr = d / F0D, j = d - rr * F0D;
             const int gy = Y0 + rr, gx = XS + 4 * j;
@@ -481,7 +486,7 @@ __global__ __launch_bounds__(256, 2) void cnn_fused_fwd_kernel(const CnnImg *__r
         const f32x4 bias = conv_bias(prm, P_B1, lane);
         const int ky = g < 3 ? g : 2;
         const int vy0 = max(0, -Y1), vy1 = min(F1H, im.h1 - Y1), vx0 = max(0, -X1), vx1 = min(F1W, im.w1 - X1);
-        for (int t = wave; t < (F1N + 15) / 16; t += 4) {
+        for (int t = wave; t < (F1N + 15) / 16; t += F_WAVES) {
             const int p = 16 * t + m;
             const int pp = p < F1N ? p : F1N - 1;
             const int r1 = pp / F1W, c1 = pp - r1 * F1W;
@@ -513,7 +518,7 @@ __global__ __launch_bounds__(256, 2) void cnn_fused_fwd_kernel(const CnnImg *__r
         }
         const int off8 = 2 * split_entry<A1P, F1J>(g >> 1, 0, 2, 2) + (g & 1);
         const int vy0 = max(0, -Y2), vy1 = min(F2H, im.h2 - Y2), vx0 = max(0, -X2), vx1 = min(F2W, im.w2 - X2);
-        for (int t2 = wave; t2 < (F2N + 15) / 16; t2 += 4) {
+        for (int t2 = wave; t2 < (F2N + 15) / 16; t2 += F_WAVES) {
             const int p = 16 * t2 + m;
             const int pp = p < F2N ? p : F2N - 1;
             const int r2 = pp / F2W, c2 = pp - r2 * F2W;
@@ -544,9 +549,9 @@ __global__ __launch_bounds__(256, 2) void cnn_fused_fwd_kernel(const CnnImg *__r
     }
     __syncthreads();
 
-    // D. conv3 (32 -> 32) + head: wave w takes 16 grid positions (w & 1) and
-    //    one 16-channel block (w >> 1); the two blocks' head sums meet in LDS
-    {
+    // D. conv3 (32 -> 32) + head: wave w < 4 takes 16 grid positions (w & 1)
+    //    and one 16-channel block (w >> 1); the two blocks' head sums meet in LDS
+    if (wave < 4) {
         const int nt = wave & 1, mb = wave >> 1;
         const int p = 16 * nt + m, r3 = p >> 3, c3 = p & 7;
         const W3 w = conv3_a(wp3, lane, 16 * mb);
@@ -1005,7 +1010,7 @@ int32_t cnn_propose(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *pyr
     uint16_t *wp2 = (uint16_t *)(ws + P->off_wp2), *wp3 = (uint16_t *)(ws + P->off_wp3);
     hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, params_bf16, wp2, wp3);
     if (P->tf > 0)
-        hipLaunchKernelGGL(cnn_fused_fwd_kernel, dim3((unsigned)P->tf), dim3(256), 0, st, P->d_img,
+        hipLaunchKernelGGL(cnn_fused_fwd_kernel, dim3((unsigned)P->tf), dim3(F_THREADS), 0, st, P->d_img,
                            P->d_pre + 7 * (P->n + 1), P->n, pyr, params_bf16, wp2, wp3, grid_logits);
     rc = check_launch("cnn_propose (forward)");
     if (rc) return rc;

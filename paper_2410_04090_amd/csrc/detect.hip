@@ -126,12 +126,15 @@ __device__ __forceinline__ bool cell_runs(const uint8_t *mask0, const LevelDev &
 }
 
 // Expand the level-0 cell mask to run flags of every cell of every level
-// (one thread per cell), so the detector reads one byte per cell.
+// (one thread per cell), so the detector reads one byte per cell; a cell
+// that does not run gets its (empty) key here, since the detector visits
+// only tiles with a running cell.  Block 0 also clears the work list's count.
 __global__ __launch_bounds__(256) void expand_mask_kernel(const ImageDev *__restrict__ imgs,
                                                           const CellChunk *__restrict__ chunks,
                                                           const uint8_t *__restrict__ mask0,
-                                                          uint8_t *__restrict__ run, int level_begin,
-                                                          int level_end) {
+                                                          uint8_t *__restrict__ run, uint32_t *__restrict__ keys,
+                                                          int32_t *__restrict__ list, int level_begin, int level_end) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) list[0] = 0;
     const CellChunk ch = chunks[blockIdx.x];
     if (ch.level < level_begin || ch.level >= level_end) return;
     const ImageDev &im = imgs[ch.image];
@@ -139,7 +142,42 @@ __global__ __launch_bounds__(256) void expand_mask_kernel(const ImageDev *__rest
     const int idx = (int)ch.first + (int)threadIdx.x;
     if (idx >= lv.ncx * lv.ncy) return;
     const int cy = idx / lv.ncx, cx = idx - cy * lv.ncx;
-    run[lv.cell_offset + idx] = cell_runs(mask0 + im.cell0_offset, im.lv[0], lv, cx, cy) ? 1 : 0;
+    const bool r = cell_runs(mask0 + im.cell0_offset, im.lv[0], lv, cx, cy);
+    run[lv.cell_offset + idx] = r ? 1 : 0;
+    if (!r) keys[lv.cell_offset + idx] = 0;
+}
+
+// Work list of the gated detector: the items (tiles) with at least one
+// running cell, as indices into the launched item range.  One thread per
+// item; each block appends its items in order at a position taken with one
+// atomic add (the order of blocks in the list does not matter: every item
+// writes only its own cells).
+__global__ __launch_bounds__(256) void gate_items_kernel(const DetItem *__restrict__ items, int n_items,
+                                                         const uint8_t *__restrict__ run, int32_t *__restrict__ list) {
+    __shared__ int s_wave[4];
+    __shared__ int s_base;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool any = false;
+    if (i < n_items) {
+        const DetItem it = items[i];
+        for (int ky = 0; ky < it.nky && !any; ky++) {
+            const uint8_t *row = run + it.cell_offset + (int64_t)(it.cy0 + ky) * it.ncx + it.cx0;
+            for (int kx = 0; kx < it.nkx; kx++) any = any || row[kx] != 0;
+        }
+    }
+    const uint64_t bal = __ballot(any);
+    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+    if (lane == 0) s_wave[wave] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int tot = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+        s_base = tot ? atomicAdd(&list[0], tot) : 0;
+    }
+    __syncthreads();
+    int before = s_base;
+    for (int w = 0; w < wave; w++) before += s_wave[w];
+    if (any) list[1 + before + below] = i;
 }
 
 // 16 consecutive bytes of a row starting at x (zero outside [0, w)).  In
@@ -217,7 +255,8 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
                                                       const uint8_t *__restrict__ pyr,
                                                       const uint8_t *__restrict__ mask,
                                                       uint32_t *__restrict__ cell_keys,
-                                                      uint16_t *__restrict__ crf, DetParams prm) {
+                                                      uint16_t *__restrict__ crf,
+                                                      const int32_t *__restrict__ list, DetParams prm) {
     __shared__ __attribute__((aligned(16))) uint32_t tile[FT_ROWS * FT_W];
     __shared__ uint16_t s_q[DET_WAVES][FT_QW];
     __shared__ uint16_t s_d[DET_WAVES][FT_DQ];
@@ -228,7 +267,16 @@ __global__ __launch_bounds__(DET_THREADS, 32 / DET_WAVES) void fast_br_kernel(co
     // level-major items in dispatch order, in groups of 16 neighbouring
     // tiles per XCD (shared halo lines hit in that XCD's L2; a contiguous
     // range per XCD would give some XCDs only the heavy level 0)
-    const DetItem it = items[xcd_group_item<16>(blockIdx.x, gridDim.x)];
+    // (gated: the grid covers every item, the list holds the running ones)
+    int item;
+    if (list) {
+        const int n_run = list[0];
+        if ((int)blockIdx.x >= n_run) return;
+        item = list[1 + xcd_group_item<16>(blockIdx.x, n_run)];
+    } else {
+        item = xcd_group_item<16>(blockIdx.x, gridDim.x);
+    }
+    const DetItem it = items[item];
     const DetItem &lv = it;                      // the level's geometry travels with the item
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -606,18 +654,18 @@ __global__ void fill_u16_kernel(uint16_t *p, int64_t n) {
 template <int PF, bool LO>
 static void launch_fast(const vsfe_batch *b, const DetItem *items, int32_t n_items, hipStream_t st,
                         const uint8_t *images, const uint8_t *pyr, const uint8_t *mask, uint32_t *keys,
-                        uint16_t *crf, const DetParams &prm) {
+                        uint16_t *crf, const int32_t *list, const DetParams &prm) {
     if (prm.p_min == 9 && prm.p_max == 13)
         hipLaunchKernelGGL((fast_br_kernel<PF, LO, true>), dim3(n_items), dim3(DET_THREADS), 0, st, b->d_images, items,
-                           images, pyr, mask, keys, crf, prm);
+                           images, pyr, mask, keys, crf, list, prm);
     else
         hipLaunchKernelGGL((fast_br_kernel<PF, LO, false>), dim3(n_items), dim3(DET_THREADS), 0, st, b->d_images, items,
-                           images, pyr, mask, keys, crf, prm);
+                           images, pyr, mask, keys, crf, list, prm);
 }
 
 int32_t detect_launch(const vsfe_ctx *ctx, const vsfe_batch *b, const DetItem *items, int32_t n_items,
                       const uint8_t *images, const uint8_t *pyr, const uint8_t *cell_mask, uint32_t *cell_keys,
-                      uint16_t *crf_debug, hipStream_t st) {
+                      uint16_t *crf_debug, const int32_t *item_list, hipStream_t st) {
     const vsfe_params &p = ctx->p;
     DetParams prm;
     prm.eps_hi = p.eps_hi;
@@ -630,12 +678,12 @@ int32_t detect_launch(const vsfe_ctx *ctx, const vsfe_batch *b, const DetItem *i
     const int pf = p.p_min >= 9 ? 2 : (p.p_min >= 5 ? 1 : 0);
     const bool lo = p.eps_lo >= 0;
     if (n_items <= 0) return VSFE_OK;
-    if (pf == 2 && lo) launch_fast<2, true>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    else if (pf == 2) launch_fast<2, false>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    else if (pf == 1 && lo) launch_fast<1, true>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    else if (pf == 1) launch_fast<1, false>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    else if (lo) launch_fast<0, true>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
-    else launch_fast<0, false>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, prm);
+    if (pf == 2 && lo) launch_fast<2, true>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, item_list, prm);
+    else if (pf == 2) launch_fast<2, false>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, item_list, prm);
+    else if (pf == 1 && lo) launch_fast<1, true>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, item_list, prm);
+    else if (pf == 1) launch_fast<1, false>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, item_list, prm);
+    else if (lo) launch_fast<0, true>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, item_list, prm);
+    else launch_fast<0, false>(b, items, n_items, st, images, pyr, cell_mask, cell_keys, crf_debug, item_list, prm);
     return check_launch("fast_br_detect");
 }
 
@@ -645,18 +693,27 @@ static int32_t detect_range(const vsfe_ctx *ctx, const vsfe_batch *b, const uint
                             const uint8_t *cell_mask, uint32_t *cell_keys, uint16_t *crf_debug, int lb, int le,
                             hipStream_t st) {
     const uint8_t *run = nullptr;
+    const int32_t *list = nullptr;
+    const int i0 = b->det_start[lb], i1 = b->det_start[le];
     if (cell_mask) {
-        if (!b->d_run) return fail(VSFE_EINVAL, "batch has no run-flag table");
+        if (!b->d_run || !b->d_item_list || b->item_list_cap < b->n_det_items)
+            return fail(VSFE_EINVAL, "batch has no gating tables");
         if (b->n_chunks > 0) {
             hipLaunchKernelGGL(expand_mask_kernel, dim3(b->n_chunks), dim3(PYCA_CHUNK), 0, st, b->d_images,
-                               b->d_chunks, cell_mask, b->d_run, lb, le);
-            const int32_t rc = check_launch("fast_br_detect (mask expansion)");
+                               b->d_chunks, cell_mask, b->d_run, cell_keys, b->d_item_list, lb, le);
+            int32_t rc = check_launch("fast_br_detect (mask expansion)");
             if (rc) return rc;
+            if (i1 > i0) {
+                hipLaunchKernelGGL(gate_items_kernel, dim3((unsigned)((i1 - i0 + 255) / 256)), dim3(256), 0, st,
+                                   b->d_det_items + i0, i1 - i0, b->d_run, b->d_item_list);
+                rc = check_launch("fast_br_detect (work list)");
+                if (rc) return rc;
+            }
+            list = b->d_item_list;
         }
         run = b->d_run;
     }
-    const int i0 = b->det_start[lb], i1 = b->det_start[le];
-    return detect_launch(ctx, b, b->d_det_items + i0, i1 - i0, images, pyr, run, cell_keys, crf_debug, st);
+    return detect_launch(ctx, b, b->d_det_items + i0, i1 - i0, images, pyr, run, cell_keys, crf_debug, list, st);
 }
 
 }  // namespace vsfe

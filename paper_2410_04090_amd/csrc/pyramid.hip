@@ -153,14 +153,13 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
 
 using namespace vsfe;
 
-extern "C" int32_t pyramid_build(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
-                                 uint8_t *pyr, int32_t *status, void *stream) {
+static int32_t build_range(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images, uint8_t *pyr,
+                           int32_t *status, int lb, int le, hipStream_t st) {
     int32_t rc = check_common(ctx, b, status);
     if (rc) return rc;
     if (!images || !pyr) return fail(VSFE_EINVAL, "null image or pyramid buffer");
     const int aligned = b->aligned_input16 && (((uintptr_t)images & 15) == 0) ? 1 : 0;
-    hipStream_t st = (hipStream_t)stream;
-    for (int l = 1; l < b->info.n_levels; l++) {
+    for (int l = lb; l < le; l++) {
         const int n = b->pyr_start[l + 1] - b->pyr_start[l];
         if (n <= 0) continue;
         hipLaunchKernelGGL(pyramid_level_kernel, dim3(n), dim3(256), 0, st, b->d_images,
@@ -169,4 +168,19 @@ extern "C" int32_t pyramid_build(const vsfe_ctx *ctx, const vsfe_batch *b, const
         if (rc) return rc;
     }
     return VSFE_OK;
+}
+
+extern "C" int32_t pyramid_build(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
+                                 uint8_t *pyr, int32_t *status, void *stream) {
+    if (!b) return fail(VSFE_EINVAL, "null batch");
+    return build_range(ctx, b, images, pyr, status, 1, b->info.n_levels, (hipStream_t)stream);
+}
+
+extern "C" int32_t pyramid_build_levels(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *images,
+                                        uint8_t *pyr, int32_t level_begin, int32_t level_end, int32_t *status,
+                                        void *stream) {
+    if (!b) return fail(VSFE_EINVAL, "null batch");
+    if (level_begin < 1 || level_end > b->info.n_levels || level_begin >= level_end)
+        return fail(VSFE_EINVAL, "level range out of 1..n_levels or empty");
+    return build_range(ctx, b, images, pyr, status, level_begin, level_end, (hipStream_t)stream);
 }

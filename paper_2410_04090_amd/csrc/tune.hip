@@ -59,6 +59,17 @@ static int32_t upload_items(const std::vector<DetItem> &v, DetItem **dst) {
     return VSFE_OK;
 }
 
+int32_t det_list_alloc(vsfe_batch *b) {
+    if (b->item_list_cap >= b->n_det_items && b->d_item_list) return VSFE_OK;
+    int32_t *d = nullptr;
+    if (hipMalloc((void **)&d, ((size_t)b->n_det_items + 1) * sizeof(int32_t)) != hipSuccess)
+        return fail(VSFE_EHIP, "hipMalloc of the gated work list failed");
+    if (b->d_item_list) (void)hipFree(b->d_item_list);
+    b->d_item_list = d;
+    b->item_list_cap = b->n_det_items;
+    return VSFE_OK;
+}
+
 // Replace the device item table after b->tile_w / b->tile_h changed.
 static int32_t det_items_refresh(vsfe_batch *b) {
     det_items_build(b);
@@ -67,7 +78,7 @@ static int32_t det_items_refresh(vsfe_batch *b) {
     if (rc) return rc;
     if (b->d_det_items) (void)hipFree(b->d_det_items);
     b->d_det_items = d;
-    return VSFE_OK;
+    return det_list_alloc(b);
 }
 
 }  // namespace vsfe
@@ -152,11 +163,11 @@ int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *i
                 break;
             }
             const int n = (int)items.size();
-            rc = detect_launch(ctx, b, d_items, n, images, pyr, nullptr, cell_keys, nullptr, st);   // warm-up
+            rc = detect_launch(ctx, b, d_items, n, images, pyr, nullptr, cell_keys, nullptr, nullptr, st);   // warm-up
             if (rc) break;
             (void)hipEventRecord(e0, st);
             for (int r = 0; r < reps && !rc; r++)
-                rc = detect_launch(ctx, b, d_items, n, images, pyr, nullptr, cell_keys, nullptr, st);
+                rc = detect_launch(ctx, b, d_items, n, images, pyr, nullptr, cell_keys, nullptr, nullptr, st);
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) rc = fail(VSFE_EHIP, "tuning run failed");
             if (rc) break;

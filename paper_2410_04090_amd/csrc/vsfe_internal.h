@@ -124,6 +124,10 @@ struct vsfe_batch {
     std::vector<vsfe::CellChunk> h_chunks;
     vsfe::CellChunk *d_chunks = nullptr;
     uint8_t *d_run = nullptr;                    // per-cell run flags of the gated detector
+    // gated detector work list: [0] = count, then the indices of the items
+    // (of the launched level range) with at least one running cell
+    int32_t *d_item_list = nullptr;
+    int32_t item_list_cap = 0;
     int32_t n_row_tab = 0;                       // stereo: first keypoint of every cell row
     int32_t *d_row_tab = nullptr;
     bool pairs_ok = false;                       // even count, equal pair sizes
@@ -178,10 +182,13 @@ void cnn_release(vsfe_batch *b);
 void det_items_level(const vsfe_batch *b, int level, int tile_w, int tile_h, std::vector<DetItem> *out);
 // rebuild every level's detector items from b->tile_w / b->tile_h (host only)
 void det_items_build(vsfe_batch *b);
+// (re)allocate the gated detector's work list for the current item count
+int32_t det_list_alloc(vsfe_batch *b);
 // launch the detector over n device items (no argument checks)
+// (item_list: nullable gated work list, [0] = count, then item indices)
 int32_t detect_launch(const vsfe_ctx *ctx, const vsfe_batch *b, const DetItem *items, int32_t n_items,
                       const uint8_t *images, const uint8_t *pyr, const uint8_t *cell_mask, uint32_t *cell_keys,
-                      uint16_t *crf_debug, hipStream_t st);
+                      uint16_t *crf_debug, const int32_t *item_list, hipStream_t st);
 
 // one-time upload of the orientation disc tables to the current device
 int32_t orb_prepare(int device);

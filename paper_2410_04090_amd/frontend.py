@@ -51,6 +51,8 @@ class Frontend:
         self.match_idx = torch.zeros(mcap, **i32)
         self.match_dist = torch.zeros(mcap, dtype=torch.int16, device=dev)
         self.match_disp = torch.zeros(mcap, dtype=torch.int16, device=dev)
+        self.refine_disp = torch.zeros(mcap, **i32)
+        self.refine_sad = torch.zeros(mcap, **i32)
         self.status = torch.zeros(1, **i32)
         self.crf = torch.zeros(max(info.crf_elems, 1), dtype=torch.int16, device=dev) if with_crf else None
         self.cell_mask = torch.ones(max(info.n_cells0, 1), **u8) if with_mask else None
@@ -132,9 +134,22 @@ class Frontend:
         describe = self.describe if describe is None else describe
         stereo = self.stereo if stereo is None else stereo
         c, b = self.ctx, self.batch
-        vsfe.pyramid_build(c, b, self.images, self.pyr, self.status, stream)
-        vsfe.cnn_propose(c, b, self.pyr, params_bf16, thresh, self.cnn_ws, self.grid_logits, self.cell_logits,
-                         self.cell_mask, self.status, stream)
+        L = self.params.n_levels
+        if L > 4:
+            # levels 1..3 feed the proposer; levels 4.. are built on a second
+            # stream while it runs, and the branches join before detection
+            st = stream if stream is not None else torch.cuda.current_stream()
+            vsfe.pyramid_build_levels(c, b, self.images, self.pyr, 1, 4, self.status, st)
+            side = self._side()
+            side.wait_stream(st)
+            vsfe.pyramid_build_levels(c, b, self.images, self.pyr, 4, L, self.status, side)
+            vsfe.cnn_propose(c, b, self.pyr, params_bf16, thresh, self.cnn_ws, self.grid_logits, self.cell_logits,
+                             self.cell_mask, self.status, st)
+            st.wait_stream(side)
+        else:
+            vsfe.pyramid_build(c, b, self.images, self.pyr, self.status, stream)
+            vsfe.cnn_propose(c, b, self.pyr, params_bf16, thresh, self.cnn_ws, self.grid_logits, self.cell_logits,
+                             self.cell_mask, self.status, stream)
         vsfe.fast_br_detect(c, b, self.images, self.pyr, self.cell_mask, self.cell_keys, self.crf, self.status,
                             stream)
         vsfe.pyca_cull_aggregate(c, b, self.cell_keys, self.workspace, self.kps, self.kp_count, self.status,
@@ -144,6 +159,24 @@ class Frontend:
             if stereo:
                 vsfe.stereo_match(c, b, self.kps, self.kp_count, self.desc, self.match_idx, self.match_dist,
                                   self.match_disp, self.status, stream)
+
+    # sub-pixel refinement window and search range (level pixels)
+    REFINE_HALF_WINDOW = 5
+    REFINE_RADIUS = 5
+
+    def refine(self, stream=None, half_window=None, search_radius=None):
+        """Sub-pixel refinement of the stereo matches (after run())."""
+        vsfe.stereo_refine(self.ctx, self.batch, self.images, self.pyr, self.kps, self.kp_count, self.match_idx,
+                           self.REFINE_HALF_WINDOW if half_window is None else half_window,
+                           self.REFINE_RADIUS if search_radius is None else search_radius,
+                           self.refine_disp, self.refine_sad, self.status, stream)
+
+    def refined(self, pair):
+        """(disparity in 1/256 native pixel or INT32_MIN, least SAD) per left keypoint."""
+        n = int(self.kp_count[2 * pair].item())
+        base = pair * self.params.n_max
+        return (self.refine_disp[base:base + n].cpu().numpy(),
+                self.refine_sad[base:base + n].cpu().numpy().view(np.uint32))
 
     def autotune(self, reps=5):
         """Pick per-level detector tiles on the uploaded batch (graphs captured

@@ -79,7 +79,9 @@ EXPORTS = ["vsfe_params_default", "vsfe_params_check", "vsfe_level_geometry", "v
            "vsfe_batch_info_get", "vsfe_batch_level_info", "vsfe_ctx_set_tile", "vsfe_last_error",
            "pyramid_build", "fast_br_detect", "fast_br_detect_levels", "pyca_cull_aggregate", "orb_describe",
            "stereo_match", "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step",
-           "vsfe_batch_tiles_get", "vsfe_batch_set_tiles", "vsfe_batch_autotune", "pyca_cull_aggregate_noalloc"]
+           "vsfe_batch_tiles_get", "vsfe_batch_set_tiles", "vsfe_batch_autotune", "pyca_cull_aggregate_noalloc",
+           "stereo_refine", "vsfe_feature_match_workspace", "feature_match",
+           "vsfe_fc_cull_stride", "fc_cull_crf", "pyramid_build_levels"]
 
 NOALLOC_MAX_CELLS = 1 << 22
 
@@ -127,20 +129,28 @@ def lib():
     L.vsfe_last_error.argtypes = []
     L.vsfe_last_error.restype = C.c_char_p
     L.pyramid_build.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pyramid_build_levels.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
     L.fast_br_detect.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.fast_br_detect_levels.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, vp]
     L.pyca_cull_aggregate.argtypes = [vp, vp, vp, vp, C.POINTER(KpSoa), vp, vp, vp]
     L.pyca_cull_aggregate_noalloc.argtypes = [vp, vp, vp, C.POINTER(KpSoa), vp, vp, vp]
     L.orb_describe.argtypes = [vp, vp, vp, vp, C.POINTER(KpSoa), vp, vp, vp, vp]
     L.stereo_match.argtypes = [vp, vp, C.POINTER(KpSoa), vp, vp, vp, vp, vp, vp, vp]
+    L.stereo_refine.argtypes = [vp, vp, vp, vp, C.POINTER(KpSoa), vp, vp, i32, i32, vp, vp, vp, vp]
+    L.vsfe_feature_match_workspace.argtypes = [vp, pi64]
+    L.feature_match.argtypes = [vp, vp, C.POINTER(KpSoa), vp, vp, C.POINTER(KpSoa), vp, vp, i32, i32, i32, i32, vp,
+                                vp, vp, vp, vp, vp]
+    L.vsfe_fc_cull_stride.argtypes = [vp, i32, i32, pi64]
+    L.fc_cull_crf.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp, vp]
     L.vsfe_cnn_info_get.argtypes = [vp, C.POINTER(CnnInfo)]
     L.cnn_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.cnn_propose.argtypes = [vp, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp]
     L.cnn_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_float, vp, vp, vp, vp]
     L.cnn_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]
-    for f in ("pyramid_build", "fast_br_detect", "fast_br_detect_levels", "pyca_cull_aggregate",
+    for f in ("pyramid_build", "pyramid_build_levels", "fast_br_detect", "fast_br_detect_levels", "pyca_cull_aggregate",
               "pyca_cull_aggregate_noalloc", "orb_describe",
-              "stereo_match", "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step"):
+              "stereo_match", "stereo_refine", "vsfe_feature_match_workspace", "feature_match", "vsfe_fc_cull_stride", "fc_cull_crf",
+              "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -271,6 +281,11 @@ def pyramid_build(ctx, b, images, pyr, status, stream=None):
     _check(lib().pyramid_build(ctx, b, _p(images), _p(pyr), _p(status), _stream(stream)))
 
 
+def pyramid_build_levels(ctx, b, images, pyr, level_begin, level_end, status, stream=None):
+    _check(lib().pyramid_build_levels(ctx, b, _p(images), _p(pyr), int(level_begin), int(level_end), _p(status),
+                                      _stream(stream)))
+
+
 def fast_br_detect(ctx, b, images, pyr, cell_mask, cell_keys, crf_debug, status, stream=None):
     _check(lib().fast_br_detect(ctx, b, _p(images), _p(pyr), _p(cell_mask), _p(cell_keys),
                                 _p(crf_debug), _p(status), _stream(stream)))
@@ -303,6 +318,39 @@ def stereo_match(ctx, b, kps, kp_count, desc, match_idx, match_dist, match_disp,
     s = kp_soa(kps)
     _check(lib().stereo_match(ctx, b, C.byref(s), _p(kp_count), _p(desc), _p(match_idx),
                               _p(match_dist), _p(match_disp), _p(status), _stream(stream)))
+
+
+def stereo_refine(ctx, b, images, pyr, kps, kp_count, match_idx, half_window, search_radius, disp_q8, sad_min,
+                  status, stream=None):
+    s = kp_soa(kps)
+    _check(lib().stereo_refine(ctx, b, _p(images), _p(pyr), C.byref(s), _p(kp_count), _p(match_idx),
+                               int(half_window), int(search_radius), _p(disp_q8), _p(sad_min), _p(status),
+                               _stream(stream)))
+
+
+def feature_match_workspace(b) -> int:
+    v = C.c_int64()
+    _check(lib().vsfe_feature_match_workspace(b, C.byref(v)))
+    return v.value
+
+
+def feature_match(ctx, b, query, query_count, query_desc, ref, ref_count, ref_desc, radius, level_band, match_th,
+                  ratio_pct, workspace, match_idx, dist1, dist2, status, stream=None):
+    sq, sr = kp_soa(query), kp_soa(ref)
+    _check(lib().feature_match(ctx, b, C.byref(sq), _p(query_count), _p(query_desc), C.byref(sr), _p(ref_count),
+                               _p(ref_desc), int(radius), int(level_band), int(match_th), int(ratio_pct),
+                               _p(workspace), _p(match_idx), _p(dist1), _p(dist2), _p(status), _stream(stream)))
+
+
+def fc_cull_stride(b, level, cell) -> int:
+    v = C.c_int64()
+    _check(lib().vsfe_fc_cull_stride(b, int(level), int(cell), C.byref(v)))
+    return v.value
+
+
+def fc_cull_crf(ctx, b, crf, level, cell, scheme, n_loc, keys, status, stream=None):
+    _check(lib().fc_cull_crf(ctx, b, _p(crf), int(level), int(cell), int(scheme), int(n_loc), _p(keys), _p(status),
+                             _stream(stream)))
 
 
 # ------------------------------------------------------------- learned proposer

@@ -154,6 +154,47 @@ def test_gated_detection_matches_oracle(fe_mod, pattern):
     run_and_compare(fe_mod, [l, r], p, pattern, full_stages=False, mask=masks)
 
 
+@pytest.mark.parametrize("kind", ["zeros", "ones", "checker", "single", "rows"])
+def test_gated_work_list_masks(fe_mod, pattern, kind):
+    """The gated launch visits only tiles with a running cell (device-built
+    work list); skipped cells must read as empty even after an ungated run
+    left keys in them, for masks from none to all and structured ones."""
+    import torch
+    l, r = scenes.stereo_pair(95, 640, 360, 120, 40)
+    p = Params()
+    ncx, ncy = 640 // 32, (360 + 31) // 32
+    m = np.zeros((ncy, ncx), np.uint8)
+    if kind == "ones":
+        m[:] = 1
+    elif kind == "checker":
+        m[(np.arange(ncy)[:, None] + np.arange(ncx)[None, :]) % 2 == 0] = 1
+    elif kind == "single":
+        m[ncy // 2, ncx // 2] = 1
+    elif kind == "rows":
+        m[::3, :] = 1
+    say("case: gated work list, mask %s (%d of %d cells)" % (kind, int(m.sum()), m.size))
+    fe = fe_mod.Frontend(p, [(640, 360)] * 2, pattern, with_mask=True)
+    try:
+        fe.upload([l, r])
+        fe.run()                                       # ungated: keys in every cell
+        fe.cell_mask.copy_(torch.from_numpy(np.concatenate([m.reshape(-1), m.reshape(-1)])))
+        fe.run(mask=fe.cell_mask)
+        torch.cuda.synchronize()
+        assert int(fe.status.item()) == 0
+        refs = []
+        for i, img in enumerate((l, r)):
+            _, ref = oracle_image(img, p, pattern, m)
+            compare_kps(ref, fe.results(i), i)
+            refs.append(ref)
+            if kind == "zeros":
+                assert len(ref["x"]) == 0
+                for lv in range(p.n_levels):
+                    assert not fe.cell_keys_level(i, lv).any()
+        compare_matches(fe, 0, refs[0], refs[1], p)
+    finally:
+        fe.close()
+
+
 def test_deterministic_repeats(fe_mod, pattern):
     import torch
     w = configs.pair_1241x376()
