@@ -340,9 +340,11 @@ int32_t stereo_refine(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *i
  * ratio_pct > 0 and a second candidate, 100 best < ratio_pct second.
  * Outputs per query slot (kp_capacity entries): match_idx (reference index
  * within the image, -1 if not accepted), dist1 / dist2 (0xFFFF if absent).
- * workspace: vsfe_feature_match_workspace() bytes of device scratch
- * (overwritten).  EINVAL: radius outside 0..255, level_band outside 0..11,
- * match_th outside 0..256, ratio_pct outside 0..100, null buffers. */
+ * workspace: vsfe_feature_match_workspace() bytes of 16-byte aligned
+ * device scratch (overwritten; it holds the references bucketed by cell with
+ * copies of their descriptors).  EINVAL: radius outside 0..255, level_band
+ * outside 0..11, match_th outside 0..256, ratio_pct outside 0..100, null
+ * buffers, a misaligned workspace. */
 int32_t vsfe_feature_match_workspace(const vsfe_batch *b, int64_t *bytes);
 int32_t feature_match(const vsfe_ctx *ctx, const vsfe_batch *b, const vsfe_kp_soa *query,
                       const int32_t *query_count, const uint32_t *query_desc, const vsfe_kp_soa *ref,

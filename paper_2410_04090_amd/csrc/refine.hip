@@ -13,20 +13,23 @@
 // native-scale disparity floor(((256 xl - (256 (xr + s*) + offset)) S_l +
 // 2^15) / 2^16) in 1/256 pixel.
 //
-// GPU mapping: a group of 16 lanes per left keypoint slot (4 per wave); lane
-// k of the group evaluates shift s = k - r over the whole window: per row it
-// assembles the window's bytes of both views as byte-aligned words from
-// aligned dword loads (v_alignbyte) and accumulates |a - b| four bytes per
-// v_sad_u8.  A 16-lane minimum of (SAD, |s|, s) picks s*; the two
-// neighbouring SADs come from their lanes; the group's first lane fits the
-// parabola.
+// GPU mapping: a group of 16 lanes per left keypoint slot (4 per wave);
+// lane k of the group takes window row k.  It loads the row's window bytes
+// of the left view and the right view's span of 2 (w + r) + 1 bytes as
+// aligned dwords once, re-bases the span to every byte offset with
+// v_alignbyte, and accumulates |a - b| four bytes per v_sad_u8 for every
+// shift.  The per-row SADs are summed over the group by recursive halving
+// (four exchange steps, 8 + 4 + 2 + 1 shuffles), which leaves the SAD of
+// shift index k in lane k.  A 16-lane minimum of (SAD, |s|, s) picks s*;
+// the two neighbouring SADs come from their lanes; the group's first lane
+// fits the parabola.
 #include <limits.h>
 
 #include "vsfe_internal.h"
 
 namespace vsfe {
 
-constexpr int RF_GROUP = 16;             // lanes per keypoint (2 r + 1 <= 15)
+constexpr int RF_GROUP = 16;             // lanes per keypoint: window rows 2 w + 1 and shifts 2 r + 1 <= 15
 constexpr int RF_MAX_W = 7, RF_MAX_R = 7;
 
 struct RefineArgs {
@@ -97,19 +100,61 @@ __global__ __launch_bounds__(256) void refine_kernel(const ImageDev *__restrict_
     const bool aligned = level > 0 || a.aligned0 != 0;
     const uint8_t *basel = (level == 0 ? images : pyr) + iml.lv[level].offset;
     const uint8_t *baser = (level == 0 ? images : pyr) + imgs[ri].lv[level].offset;
-    const int s = k - r;
-    const bool active = k <= 2 * r;
-    uint32_t acc = 0;
-    if (active) {
-        for (int dy = -w; dy <= w; dy++) {
-            const int64_t ro = (int64_t)(yl + dy) * lv.pitch;
-            uint32_t lw[4], rw[4];
-            window_words(basel + ro, xl - w, lv.w, aligned, nb, lw);
-            window_words(baser + ro, xr + s - w, lv.w, aligned, nb, rw);
+    // col[t]: this lane's window row, SAD at shift s = t - r
+    uint32_t col[RF_GROUP];
 #pragma unroll
-            for (int q = 0; q < 4; q++) acc = __builtin_amdgcn_sad_u8(lw[q], rw[q], acc);
+    for (int t = 0; t < RF_GROUP; t++) col[t] = 0;
+    if (k < nb) {
+        const int64_t ro = (int64_t)(yl + k - w) * lv.pitch;
+        uint32_t lw[4];
+        window_words(basel + ro, xl - w, lv.w, aligned, nb, lw);
+        // the right row's span xr - r - w .. xr + r + w, re-based to byte 0
+        // (e0) and to bytes 1..3 (e1..e3): the window at shift index t is
+        // the four words from byte t of the span
+        const int x0 = xr - r - w, need = (x0 & 3) + nb + 2 * r;
+        const int sh = x0 & 3;
+        uint32_t d[9];
+#pragma unroll
+        for (int q = 0; q < 9; q++) d[q] = 4 * q < need ? row_dword(baser + ro, (x0 & ~3) + 4 * q, lv.w, aligned) : 0u;
+        uint32_t e[4][8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) e[0][q] = __builtin_amdgcn_alignbyte(d[q + 1], d[q], (uint32_t)sh);
+#pragma unroll
+        for (int u = 1; u < 4; u++)
+#pragma unroll
+            for (int q = 0; q < 7; q++) e[u][q] = __builtin_amdgcn_alignbyte(e[0][q + 1], e[0][q], (uint32_t)u);
+        uint32_t m[4];                                    // window bytes of each word
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int left = nb - 4 * q;
+            m[q] = left >= 4 ? 0xFFFFFFFFu : (left <= 0 ? 0u : (1u << (8 * left)) - 1u);
+        }
+#pragma unroll
+        for (int t = 0; t < 2 * RF_MAX_R + 1; t++) {
+            const int q = t >> 2, u = t & 3;
+            uint32_t acc = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc = __builtin_amdgcn_sad_u8(lw[j], e[u][q + j] & m[j], acc);
+            col[t] = t <= 2 * r ? acc : 0u;
         }
     }
+    // column sums over the group's 16 rows by recursive halving: after the
+    // step that exchanges with lane k ^ h, lane k holds the partial sums of
+    // the shift indices whose bit h matches its own, so lane k ends with the
+    // full SAD of shift index k
+#pragma unroll
+    for (int h = RF_GROUP / 2; h > 0; h >>= 1) {
+        const bool up = (k & h) != 0;
+#pragma unroll
+        for (int j = 0; j < h; j++) {
+            const uint32_t keep = up ? col[j + h] : col[j];
+            const uint32_t give = up ? col[j] : col[j + h];
+            col[j] = keep + (uint32_t)__shfl_xor((int)give, h, RF_GROUP);
+        }
+    }
+    const uint32_t acc = col[0];
+    const int s = k - r;
+    const bool active = k <= 2 * r;
     // least (SAD, |s|, s) over the group: SAD < 2^16 (15 x 15 x 255), |s|, s + 8 in a byte each
     const uint32_t as = (uint32_t)(s < 0 ? -s : s);
     uint32_t key = active ? (acc << 16) | (as << 8) | (uint32_t)(s + 8) : 0xFFFFFFFFu;
