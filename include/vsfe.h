@@ -379,8 +379,12 @@ int32_t fc_cull_crf(const vsfe_ctx *ctx, const vsfe_batch *b, const uint16_t *cr
  * stride-2 convolutions with zero padding 1 (1 -> 16 -> 32 -> 32 channels,
  * ReLU) and a 1x1 head (32 -> 1), one logit per stride-8 grid position.
  * Parameters: one vector of 14081 values, OIHW weights then biases per
- * layer (w1 b1 w2 b2 w3 b3 w4 b4); the kernels read a bfloat16 copy and
- * keep bfloat16 activations with float32 sums.  Grid logits are float32,
+ * layer (w1 b1 w2 b2 w3 b3 w4 b4); the kernels read a bfloat16 copy, so
+ * the network evaluated is the bfloat16-valued one, with float32 sums.
+ * cnn_forward (training) feeds each convolution its float32 input as a
+ * bfloat16 value + remainder pair (logits within about 1e-4 of float32);
+ * cnn_propose (inference) stores activations as float16 (within 1e-2 of
+ * float32; weights beyond +-65504 saturate there).  Grid logits are float32,
  * images' grids back to back in image order, row-major.  All calls need
  * n_levels >= 4 (EINVAL otherwise) and a workspace of workspace_bytes. */
 typedef struct vsfe_cnn_info {

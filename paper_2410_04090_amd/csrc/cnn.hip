@@ -9,29 +9,32 @@
 // vector, OIHW weights followed by biases per layer; the kernels read its
 // bfloat16 copy, so the network evaluated is the bfloat16-valued one.
 //
-// Precision.  Every product runs on the bfloat16 matrix cores with float32
-// accumulation.  The input (I - 128) / 128 and the weights are exact in
-// bfloat16; an activation is carried as two bfloat16 values, its rounding
-// hi and the rounding of the remainder lo (hi + lo holds about 16
-// significant bits), and each convolution adds W hi and W lo in separate
-// accumulator chains.  With one bfloat16 per activation the logits of the
-// trained networks differ from a float32 forward by up to 0.03; with the
-// pair they stay within 1e-2 (about 1e-4 in practice).  The 1x1 head reads
-// conv3's float32 output directly.
+// Precision.  The input (I - 128) / 128 and the weights are exact in both
+// half formats.  Every product runs on the matrix cores with float32
+// accumulation; what differs is how an activation enters the next layer:
+//  * inference (cnn_propose) stores it as float16 (11 significant bits):
+//    the logits of the packaged trained networks stay within 5e-3 of a
+//    float64 forward (a single bfloat16 would give up to 0.03);
+//  * training (cnn_forward, before cnn_backward) keeps float32 activations
+//    and feeds each convolution a bfloat16 value and remainder pair (hi +
+//    lo, about 16 significant bits) in separate accumulator chains, so the
+//    gradients see logits within about 1e-4 of float32.
+// The 1x1 head reads conv3's float32 output directly in both.
 //
-//  * conv1 (K = 9 taps) runs on v_mfma_f32_16x16x16_bf16: lane group g
-//    takes tap row g as the K slots (input columns 2x - 2 .. 2x + 1, the
-//    first with a zero weight, so a lane reads two aligned dwords);
-//  * conv2 (K = 144) and conv3 (K = 288) are implicit GEMMs on
-//    v_mfma_f32_16x16x32_bf16 (conv2's ninth tap on 16x16x16): weights are
-//    the A operand (row = output channel), activations the B operand
-//    (column = output pixel, 8 channels of one tap per lane);
-//  * inference (cnn_propose) runs the three layers and the head fused in
-//    one kernel per 4 x 8 tile of grid positions, activations in LDS in an
-//    even / odd column split layout (stride-2 reads of 16 consecutive
-//    output pixels hit consecutive 16-byte entries); the layer-by-layer
-//    kernels (cnn_forward) keep float32 activations for training and split
-//    them the same way, so both give bit-identical logits;
+//  * conv1 (K = 9 taps) runs on the 16x16x16 matrix instruction: lane
+//    group g takes tap row g as the K slots (input columns 2x - 2 .. 2x + 1,
+//    the first with a zero weight);
+//  * conv2 (K = 144) and conv3 (K = 288) are implicit GEMMs on the
+//    16x16x32 instruction (conv2's ninth tap on 16x16x16): weights are the
+//    A operand (row = output channel), activations the B operand (column =
+//    output pixel, 8 channels of one tap per lane);
+//  * inference runs the three layers and the head fused in one persistent
+//    kernel over 6 x 7 tiles of grid positions (activations in LDS, conv1
+//    and conv2 in even / odd column planes so that the stride-2 reads of
+//    the next layer take consecutive entries).  Two phases per tile: conv1
+//    of tile k beside conv3 + head of tile k - 1, then conv2 of tile k
+//    beside the staging of tile k + 1, whose input was fetched a phase
+//    earlier, and the fetch of tile k + 2;
 //  * cell logits: per native-scale cell, the maximum over the grid
 //    positions whose projected centre ((8 j + 4) S_3 + 2^15) >> 16 falls in
 //    it (a cell with none is always kept);
@@ -41,6 +44,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "vsfe_internal.h"
 
@@ -65,18 +69,96 @@ struct CnnPlan {
     std::vector<int32_t> h_pre;
     int32_t *d_pre = nullptr;
     int64_t px1 = 0, px2 = 0, px4 = 0, t2 = 0, t4 = 0, cells = 0, t1 = 0, tf = 0;
-    int64_t off_wp2 = 0, off_wp3 = 0, off_a1 = 0, off_a2 = 0, off_a3 = 0, off_g1 = 0, off_g2 = 0, off_g3 = 0,
+    int64_t off_wp2 = 0, off_wp3 = 0, off_hp1 = 0, off_hp2 = 0, off_hp3 = 0, off_a1 = 0, off_a2 = 0, off_a3 = 0, off_g1 = 0, off_g2 = 0, off_g3 = 0,
             off_dz = 0, off_lz = 0, off_part = 0, total = 0;
 };
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef short i16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf(uint16_t v) { return __builtin_bit_cast(float, (uint32_t)v << 16); }
 __device__ __forceinline__ uint16_t to_bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+__device__ __forceinline__ f32x4 relu4(f32x4 v) {
+    f32x4 r;
+#pragma unroll
+    for (int i = 0; i < 4; i++) r[i] = fmaxf(v[i], 0.0f);
+    return r;
+}
+
+// the input (I - 128) / 128 of byte b of v: exact in float32, bfloat16 and float16
+__device__ __forceinline__ float x_byte(uint32_t v, int b) {
+    return fmaf((float)((v >> (8 * b)) & 255u), 1.0f / 128.0f, -1.0f);
+}
+
+// largest i with pre[i] <= g (pre is nondecreasing, pre[0] = 0)
+__device__ __forceinline__ int find_image(const int32_t *pre, int n, int64_t g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ f32x4 splat4(float v) {
+    const f32x4 r = {v, v, v, v};
+    return r;
+}
+
+// per-lane biases (the accumulator's start): channels at + 4 g .. + 3
+__device__ __forceinline__ f32x4 conv_bias(const uint16_t *prm, int at, int lane) {
+    const int g = lane >> 4;
+    f32x4 b;
+#pragma unroll
+    for (int r = 0; r < 4; r++) b[r] = bf(prm[at + 4 * g + r]);
+    return b;
+}
+
+// MFMA lane layout (16 x 16 output tiles): lane l works on output pixel
+// l % 16 and K slice g = l / 16; its accumulator holds output channels
+// 4 g .. 4 g + 3 of its 16-channel block.
+
+// Repack the weights: bfloat16 conv2 / conv3 as [co][tap][ci] for the
+// training forward, and float16 copies for inference (saturated to the
+// largest finite float16): conv1 [g][c][4] (lane c + 16 g: tap row g of
+// channel c as K slots (0, w[g][0], w[g][1], w[g][2]), group 3 zero), conv2
+// and conv3 [co][tap][ci].
+__global__ void cnn_pack_kernel(const uint16_t *__restrict__ prm, uint16_t *__restrict__ wp2, uint16_t *__restrict__ wp3,
+                                uint16_t *__restrict__ hp1, uint16_t *__restrict__ hp2, uint16_t *__restrict__ hp3) {
+    auto to_h = [](float f) { return __builtin_bit_cast(uint16_t, (_Float16)fminf(fmaxf(f, -65504.f), 65504.f)); };
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 16 * 4 * 4) {
+        const int g = i / 64, c = (i / 4) % 16, s = i % 4;
+        hp1[i] = (g < 3 && s > 0) ? to_h(bf(prm[P_W1 + c * 9 + g * 3 + s - 1])) : (uint16_t)0;
+    }
+    if (i < 32 * 9 * 16) {
+        const int co = i / (9 * 16), t = (i / 16) % 9, ci = i % 16;
+        const uint16_t w = prm[P_W2 + (co * 16 + ci) * 9 + t];
+        wp2[i] = w;
+        hp2[i] = to_h(bf(w));
+    }
+    if (i < 32 * 9 * 32) {
+        const int co = i / (9 * 32), t = (i / 32) % 9, ci = i % 32;
+        const uint16_t w = prm[P_W3 + (co * 32 + ci) * 9 + t];
+        wp3[i] = w;
+        hp3[i] = to_h(bf(w));
+    }
+}
+
+// ---- training forward (cnn_forward): layer by layer through HBM with
+// float32 activations, each convolution input carried as a bfloat16 value
+// + remainder pair (hi + lo, about 16 significant bits) on the bfloat16
+// matrix cores, so that the gradients of the training loop see logits
+// within about 1e-4 of a float32 forward
+namespace tr {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ float bf_lo(uint32_t v) { return __builtin_bit_cast(float, v << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t v) { return __builtin_bit_cast(float, v & 0xFFFF0000u); }
 
@@ -107,36 +189,6 @@ __device__ __forceinline__ void split8(float4 a, float4 b, uint4 *hi, uint4 *lo)
     split2(b.z, b.w, &hi->w, &lo->w);
 }
 
-__device__ __forceinline__ f32x4 relu4(f32x4 v) {
-    f32x4 r;
-#pragma unroll
-    for (int i = 0; i < 4; i++) r[i] = fmaxf(v[i], 0.0f);
-    return r;
-}
-
-// the input (I - 128) / 128 of byte b of v: exact in float32 and bfloat16
-__device__ __forceinline__ float x_byte(uint32_t v, int b) {
-    float f;
-    switch (b) {
-        case 0: f = (float)(v & 255u); break;
-        case 1: f = (float)((v >> 8) & 255u); break;
-        case 2: f = (float)((v >> 16) & 255u); break;
-        default: f = (float)(v >> 24); break;
-    }
-    return fmaf(f, 1.0f / 128.0f, -1.0f);
-}
-
-// largest i with pre[i] <= g (pre is nondecreasing, pre[0] = 0)
-__device__ __forceinline__ int find_image(const int32_t *pre, int n, int64_t g) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ f32x4 mfma16(i16x4 a, i16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -145,29 +197,6 @@ __device__ __forceinline__ f32x4 mfma32(uint4 a, uint4 b, f32x4 c) {
                                                   0);
 }
 __device__ __forceinline__ i16x4 as_i16x4(uint2 v) { return __builtin_bit_cast(i16x4, v); }
-
-__device__ __forceinline__ f32x4 splat4(float v) {
-    const f32x4 r = {v, v, v, v};
-    return r;
-}
-
-// ------------------------------------------------------------------ forward
-// MFMA lane layout (16 x 16 output tiles): lane l works on output pixel
-// l % 16 and K slice g = l / 16; its accumulator holds output channels
-// 4 g .. 4 g + 3 (+ 16 for the second 16-channel block).
-
-// Repack conv2 / conv3 weights from OIHW to [co][tap][ci] (bf16).
-__global__ void cnn_pack_kernel(const uint16_t *__restrict__ prm, uint16_t *__restrict__ wp2, uint16_t *__restrict__ wp3) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 32 * 9 * 16) {
-        const int co = i / (9 * 16), t = (i / 16) % 9, ci = i % 16;
-        wp2[i] = prm[P_W2 + (co * 16 + ci) * 9 + t];
-    }
-    if (i < 32 * 9 * 32) {
-        const int co = i / (9 * 32), t = (i / 32) % 9, ci = i % 32;
-        wp3[i] = prm[P_W3 + (co * 32 + ci) * 9 + t];
-    }
-}
 
 // conv1 A operand: lane (channel c = l % 16, group g = l / 16).  Group g < 3
 // holds tap row g as K slots (0, w[g][0], w[g][1], w[g][2]); group 3 is zero.
@@ -250,15 +279,6 @@ __device__ __forceinline__ f32x4 conv3_mfma(const W3 &w, const B3 &b, f32x4 bias
         l = mfma32(w.t[t], b.l[t], l);
     }
     return h + l;
-}
-
-// per-lane biases (the accumulator's start): channels at + 4 g .. + 3
-__device__ __forceinline__ f32x4 conv_bias(const uint16_t *prm, int at, int lane) {
-    const int g = lane >> 4;
-    f32x4 b;
-#pragma unroll
-    for (int r = 0; r < 4; r++) b[r] = bf(prm[at + 4 * g + r]);
-    return b;
 }
 
 // 1x1 head partial of one 16-channel block (after ReLU): sum over the
@@ -399,180 +419,421 @@ __global__ __launch_bounds__(256) void cnn_conv3_kernel(const CnnImg *__restrict
     }
 }
 
-// ---- fused inference forward: one 256-thread block computes a 4 x 8 tile
-// of grid logits with every activation in LDS.  Windows (rows x columns):
-// input 39 x 72 (global columns 8 X3 - 8 ..), conv1 19 x 35, conv2 9 x 17;
-// positions outside an activation map are its zero padding.
-constexpr int F3H = 4, F3W = 8;
-constexpr int F2H = 2 * F3H + 1, F2W = 2 * F3W + 1;      // 9 x 17
-constexpr int F1H = 2 * F2H + 1, F1W = 2 * F2W + 1;      // 19 x 35
-constexpr int F0H = 2 * F1H + 1, F0C = 2 * F1W + 2;      // 39 x 72
-constexpr int F0D = F0C / 4;                             // input dwords per row (18)
-constexpr int F1J = (F1W + 1) / 2, F2J = (F2W + 1) / 2;  // column pairs: 18, 9
-constexpr int A1P = F1H * F1J;                           // a1 entries per plane (342)
-constexpr int A2P = F2H * F2J;                           // a2 entries per plane (81)
-constexpr int A1N = 8 * A1P;                             // planes: 2 groups x (hi, lo) x 2 parities
-constexpr int A2N = 16 * A2P;                            // planes: 4 groups x (hi, lo) x 2 parities
-constexpr int F1N = F1H * F1W, F2N = F2H * F2W;          // 665, 153
-static_assert(F0H * F0C * 2 <= A2N * 16, "the staged input fits in the conv2 buffer");
-// 8 waves per block: with two blocks per CU (LDS) that is four waves per
-// SIMD, enough to overlap one block's barriers and loads with the other's
-// matrix work
-constexpr int F_WAVES = 8, F_THREADS = 64 * F_WAVES;
-constexpr int F_LD = (F0H * F0D + F_THREADS - 1) / F_THREADS;   // input dwords per thread (2)
+}  // namespace tr
 
-// 16-byte entry of 8 channels (group g, part h = 0 hi / 1 lo) of position
-// (r, c) in an even / odd column split layout with `planeN` entries per plane
-template <int P, int J>
-__device__ __forceinline__ int split_entry(int g, int h, int r, int c) {
-    return ((g * 2 + h) * 2 + (c & 1)) * P + r * J + (c >> 1);
+// ---- inference (cnn_propose): activations stored as float16 (11
+// significant bits) on the float16 matrix cores, float32 sums
+namespace inf {
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+
+// two floats as packed float16, round to nearest even (v_cvt_pk_f16_f32)
+__device__ __forceinline__ uint32_t pk_h(float a, float b) {
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
 }
 
-__global__ __launch_bounds__(F_THREADS, 2) void cnn_fused_fwd_kernel(const CnnImg *__restrict__ imgs,
-                                                               const int32_t *__restrict__ pre_tiles, int n,
-                                                               const uint8_t *__restrict__ pyr,
-                                                               const uint16_t *__restrict__ prm,
-                                                               const uint16_t *__restrict__ wp2,
-                                                               const uint16_t *__restrict__ wp3, float *__restrict__ z) {
-    __shared__ uint4 s_a1[A1N];
-    __shared__ uint4 s_u[A2N];               // staged input, then conv2's output
-    __shared__ float s_head[2][32];
-    uint32_t *const s_in = (uint32_t *)s_u;  // input as bf16 pairs, F0C / 2 dwords per row
-    uint2 *const s_a1h = (uint2 *)s_a1;
-    uint2 *const s_a2h = (uint2 *)s_u;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+// ReLU of a packed float16 pair (after rounding: max(round(x), 0) equals
+// round(max(x, 0)) up to the sign of zero)
+__device__ __forceinline__ uint32_t relu_h2(uint32_t v) {
+    const f16x2 z = {(_Float16)0.f, (_Float16)0.f};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(f16x2, v), z));
+}
+
+// 4 accumulator values after ReLU as float16
+__device__ __forceinline__ uint2 relu_h4(f32x4 v) {
+    return make_uint2(relu_h2(pk_h(v[0], v[1])), relu_h2(pk_h(v[2], v[3])));
+}
+
+// 8 float32 activations (already >= 0) as float16
+__device__ __forceinline__ uint4 h8(float4 a, float4 b) {
+    return make_uint4(pk_h(a.x, a.y), pk_h(a.z, a.w), pk_h(b.x, b.y), pk_h(b.z, b.w));
+}
+
+// (I - 128) / 128 of the four bytes of v as two float16 pairs: the half
+// with bits 0x6400 | I is 1024 + I, and (1024 + I) / 128 - 9 is exact
+__device__ __forceinline__ uint2 x_h4(uint32_t v) {
+    const f16x2 s = {(_Float16)0.0078125f, (_Float16)0.0078125f}, o = {(_Float16)-9.f, (_Float16)-9.f};
+    const f16x2 a = __builtin_bit_cast(f16x2, __builtin_amdgcn_perm(v, 0x64646464u, 0x00050004u));
+    const f16x2 b = __builtin_bit_cast(f16x2, __builtin_amdgcn_perm(v, 0x64646464u, 0x00070006u));
+    return make_uint2(__builtin_bit_cast(uint32_t, __builtin_elementwise_fma(a, s, o)),
+                      __builtin_bit_cast(uint32_t, __builtin_elementwise_fma(b, s, o)));
+}
+
+__device__ __forceinline__ f32x4 mfma16(uint2 a, uint2 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(f16x4, a), __builtin_bit_cast(f16x4, b), c, 0, 0,
+                                                 0);
+}
+__device__ __forceinline__ f32x4 mfma32(uint4 a, uint4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0,
+                                                 0);
+}
+
+// conv1 A operand of a lane (channel l % 16, tap row l / 16)
+__device__ __forceinline__ uint2 conv1_a(const uint16_t *wp1, int lane) {
+    return *(const uint2 *)(wp1 + 4 * lane);
+}
+
+// Weights of one 16-channel block (rows co0 .. co0 + 15) of conv2: four
+// 32-wide K chunks (taps 2c and 2c + 1, 16 channels each; lane group g takes
+// tap 2c + g / 2, channels 8 (g & 1) .. + 7) and tap 8 on 16 K (channels
+// 4 g .. 4 g + 3).
+struct W2 {
+    uint4 c[4];
+    uint2 t8;
+};
+__device__ __forceinline__ W2 conv2_a(const uint16_t *wp2, int lane, int co0) {
     const int m = lane & 15, g = lane >> 4;
-    const int bt = xcd_item(blockIdx.x, gridDim.x);
-    const int i = find_image(pre_tiles, n, bt);
-    const CnnImg im = imgs[i];
-    const int lt = bt - pre_tiles[i];
+    W2 w;
+#pragma unroll
+    for (int c = 0; c < 4; c++) w.c[c] = *(const uint4 *)(wp2 + ((co0 + m) * 9 + 2 * c + (g >> 1)) * 16 + 8 * (g & 1));
+    w.t8 = *(const uint2 *)(wp2 + ((co0 + m) * 9 + 8) * 16 + 4 * g);
+    return w;
+}
+
+// conv3 weights of one 16-channel block: tap t, lane group g -> channels 8 g .. 8 g + 7
+struct W3 {
+    uint4 t[9];
+};
+__device__ __forceinline__ W3 conv3_a(const uint16_t *wp3, int lane, int co0) {
+    const int m = lane & 15, g = lane >> 4;
+    W3 w;
+#pragma unroll
+    for (int t = 0; t < 9; t++) w.t[t] = *(const uint4 *)(wp3 + ((co0 + m) * 9 + t) * 32 + 8 * g);
+    return w;
+}
+
+// B operands of one conv2 output pixel (per lane: its K slice)
+struct B2 {
+    uint4 c[4];
+    uint2 t8;
+};
+
+// one 16-channel block of conv2 / conv3: the bias starts the chain, then
+// the K chunks in tap order (the same order in the fused and the
+// layer-by-layer kernels)
+__device__ __forceinline__ f32x4 conv2_mfma(const W2 &w, const B2 &b, f32x4 bias) {
+    f32x4 acc = bias;
+#pragma unroll
+    for (int c = 0; c < 4; c++) acc = mfma32(w.c[c], b.c[c], acc);
+    return mfma16(w.t8, b.t8, acc);
+}
+
+// 1x1 head weights of a lane's 4 channels in block co0
+__device__ __forceinline__ f32x4 head_w(const uint16_t *prm, int co0, int lane) {
+    return conv_bias(prm, P_W4 + co0, lane);
+}
+
+// 1x1 head partial of one 16-channel block (after ReLU): sum over the
+// lane's 4 channels, then over the 4 lane groups (fixed order); every lane
+// of column m ends with the block's sum for pixel m
+__device__ __forceinline__ float head16(f32x4 a, f32x4 w) {
+    float s = 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; r++) s = fmaf(w[r], a[r], s);
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return s;
+}
+
+// ---- fused inference forward: a persistent 256-thread block walks 6 x 7
+// tiles of grid positions with every activation in LDS (float16).  Windows
+// (rows x columns) of a tile at grid (Y3, X3): conv2 13 x 15 from
+// (2 Y3 - 1, 2 X3 - 1), conv1 27 x 31, input 55 x 68 from (8 Y3 - 7,
+// 8 X3 - 8); positions outside an activation map are its zero padding.
+// conv1 and conv2 are stored in even / odd column planes (entry = (parity,
+// row, column pair)) so that the stride-2 reads of the next layer take 16
+// consecutive entries; each plane has one pad column, never read.
+//
+// Work per tile (4 waves):
+//  * conv1: unit = (row, parity), 16 pixels x 16 channels; wave w has
+//    parity w & 1 and rows 0..11 (w < 2) or 12..26 (w >= 2);
+//  * conv2: unit = one row (15 pixels) x both 16-channel blocks, so every
+//    operand read from LDS feeds two products; wave w has rows w + 4 i;
+//  * conv3 + head: unit = (16 positions, one 16-channel block); wave w has
+//    block w & 1 and position groups (w >> 1) + 2 i (two for waves 0 and 1,
+//    one for waves 2 and 3, which take three more conv1 units instead).
+constexpr int F3H = 6, F3W = 7;
+constexpr int F2H = 2 * F3H + 1, F2W = 2 * F3W + 1;      // 13 x 15
+constexpr int F1H = 2 * F2H + 1, F1W = 2 * F2W + 1;      // 27 x 31
+constexpr int F0H = 2 * F1H + 1;                         // 55 input rows
+constexpr int F1J = 16, F2J = 8;                         // column pairs per plane
+static_assert(2 * F1J == F1W + 1 && 2 * F2J == F2W + 1, "one pad column per plane");
+constexpr int F0D = 17;                                  // input dwords per row (68 columns)
+constexpr int F0S = 8 * F0D;                             // staged row stride (bytes, float16)
+constexpr int A1E = 2 * F1H * F1J;                       // conv1 entries (864) of 32 bytes
+constexpr int A2E = 2 * F2H * F2J;                       // conv2 entries (208) of 64 bytes
+constexpr int F_WAVES = 4, F_THREADS = 64 * F_WAVES;
+constexpr int F_LD = (F0H * F0D + F_THREADS - 1) / F_THREADS;   // input dwords per thread (4)
+constexpr int F_NPOS = F3H * F3W;                        // 42 grid positions
+constexpr int F_R1A = 12, F_R1B = F1H - F_R1A;           // conv1 rows of waves 0, 1 / 2, 3
+constexpr int F_NT = (F_NPOS + 15) / 16;                 // conv3 position groups (3)
+constexpr int F_BLOCKS_PER_CU = 3;
+static_assert(F_R1B - F_R1A == 3 && F_NT == 3, "the conv1 / conv3 balance below assumes these counts");
+
+// geometry of one tile: its image and grid origin (uniform)
+struct FTile {
+    int img, Y3, X3;
+};
+
+__device__ __forceinline__ FTile fused_tile(const CnnImg *imgs, const int32_t *pre, int n, int t, int &cursor) {
+    while (cursor + 1 < n && pre[cursor + 1] <= t) cursor++;
+    const CnnImg &im = imgs[cursor];
     const int ntx = (im.w4 + F3W - 1) / F3W;
-    const int Y3 = (lt / ntx) * F3H, X3 = (lt % ntx) * F3W;
-    const int Y2 = 2 * Y3 - 1, X2 = 2 * X3 - 1, Y1 = 2 * Y2 - 1, X1 = 2 * X2 - 1, Y0 = 2 * Y1 - 1;
-    const int XS = 8 * X3 - 8;                // global column of staged column 0 (a multiple of 8)
+    const int lt = t - pre[cursor], ty = lt / ntx;
+    return FTile{cursor, ty * F3H, (lt - ty * ntx) * F3W};
+}
 
-    // A. input window (I - 128) / 128 as bfloat16; rows start on 64-byte
-    //    boundaries and XS is a multiple of 4, so the window is read as
-    //    aligned dwords (bytes past the level width are zero padding)
-    {
-        uint32_t v[F_LD];
+// the input dwords of a tile this thread stages (zero outside the level)
+__device__ __forceinline__ void fused_fetch(const uint8_t *pyr, const CnnImg &im, const FTile &f, const int *rr,
+                                            const int *jj, uint32_t *v) {
+    const int Y0 = 8 * f.Y3 - 7, XS = 8 * f.X3 - 8;
+    const uint8_t *base = pyr + im.lvl3;
+    const bool interior = Y0 >= 0 && Y0 + F0H <= im.h3 && XS >= 0 && XS + 4 * F0D <= im.w3;
+    if (interior) {
+#pragma unroll
+        for (int k = 0; k < F_LD; k++)
+            v[k] = rr[k] < F0H ? *(const uint32_t *)(base + (uint32_t)((Y0 + rr[k]) * im.pitch3 + XS + 4 * jj[k])) : 0u;
+    } else {
 #pragma unroll
         for (int k = 0; k < F_LD; k++) {
-            const int d = tid + F_THREADS * k;
-            const int rr = d / F0D, j = d - rr * F0D;
-            const int gy = Y0 + rr, gx = XS + 4 * j;
-            const bool ok = d < F0H * F0D && gy >= 0 && gy < im.h3 && gx >= 0 && gx < im.w3;
-            v[k] = ok ? *(const uint32_t *)(pyr + im.lvl3 + (int64_t)gy * im.pitch3 + gx) : 0u;
+            const int gy = Y0 + rr[k], gx = XS + 4 * jj[k];
+            const bool ok = rr[k] < F0H && gy >= 0 && gy < im.h3 && gx >= 0 && gx < im.w3;
+            v[k] = ok ? *(const uint32_t *)(base + (uint32_t)(gy * im.pitch3 + gx)) : 0u;
         }
-#pragma unroll
-        for (int k = 0; k < F_LD; k++) {
-            const int d = tid + F_THREADS * k;
-            if (d >= F0H * F0D) continue;
-            const int rr = d / F0D, j = d - rr * F0D;
-            const int gy = Y0 + rr, gx = XS + 4 * j;
-            const bool row_in = gy >= 0 && gy < im.h3 && gx >= 0;
-            float x[4];
-#pragma unroll
-            for (int b = 0; b < 4; b++) x[b] = row_in && gx + b < im.w3 ? x_byte(v[k], b) : 0.f;
-            *(uint2 *)(s_in + rr * (F0C / 2) + 2 * j) = make_uint2(pk_bf(x[0], x[1]), pk_bf(x[2], x[3]));
-        }
-    }
-    __syncthreads();
-
-    // B. conv1: one 16-pixel tile per MFMA; lane group g reads its tap row
-    //    (input columns 2 c - 2 .. 2 c + 1 of the window: two aligned dwords)
-    {
-        const i16x4 w = conv1_a(prm, lane);
-        const f32x4 bias = conv_bias(prm, P_B1, lane);
-        const int ky = g < 3 ? g : 2;
-        const int vy0 = max(0, -Y1), vy1 = min(F1H, im.h1 - Y1), vx0 = max(0, -X1), vx1 = min(F1W, im.w1 - X1);
-        for (int t = wave; t < (F1N + 15) / 16; t += F_WAVES) {
-            const int p = 16 * t + m;
-            const int pp = p < F1N ? p : F1N - 1;
-            const int r1 = pp / F1W, c1 = pp - r1 * F1W;
-            const uint32_t *src = s_in + (2 * r1 + ky) * (F0C / 2) + c1;
-            const uint2 xb = make_uint2(src[0], src[1]);
-            f32x4 a = relu4(mfma16(w, as_i16x4(xb), bias));
-            if (p < F1N) {
-                const bool in = r1 >= vy0 && r1 < vy1 && c1 >= vx0 && c1 < vx1;
-                if (!in) a = splat4(0.f);
-                uint2 hi, lo;
-                split4(a, &hi, &lo);
-                s_a1h[2 * split_entry<A1P, F1J>(g >> 1, 0, r1, c1) + (g & 1)] = hi;
-                s_a1h[2 * split_entry<A1P, F1J>(g >> 1, 1, r1, c1) + (g & 1)] = lo;
-            }
-        }
-    }
-    __syncthreads();
-
-    // C. conv2 (16 -> 32): both 16-channel blocks per wave; per lane the
-    //    entry offsets of its K slices are fixed, the pixel adds a base
-    {
-        const W2 wa = conv2_a(wp2, lane, 0), wb = conv2_a(wp2, lane, 16);
-        const f32x4 ba = conv_bias(prm, P_B2, lane), bb = conv_bias(prm, P_B2 + 16, lane);
-        int off[4];
-#pragma unroll
-        for (int c = 0; c < 4; c++) {
-            const int t = 2 * c + (g >> 1), ky = t / 3, kx = t % 3;
-            off[c] = split_entry<A1P, F1J>(g & 1, 0, ky, kx);          // (r, c) = (ky, kx): parity kx & 1, pair kx >> 1
-        }
-        const int off8 = 2 * split_entry<A1P, F1J>(g >> 1, 0, 2, 2) + (g & 1);
-        const int vy0 = max(0, -Y2), vy1 = min(F2H, im.h2 - Y2), vx0 = max(0, -X2), vx1 = min(F2W, im.w2 - X2);
-        for (int t2 = wave; t2 < (F2N + 15) / 16; t2 += F_WAVES) {
-            const int p = 16 * t2 + m;
-            const int pp = p < F2N ? p : F2N - 1;
-            const int r2 = pp / F2W, c2 = pp - r2 * F2W;
-            const int base = 2 * r2 * F1J + c2;                        // input (2 r2, 2 c2): row 2 r2, pair c2
-            B2 b;
-#pragma unroll
-            for (int c = 0; c < 4; c++) {
-                b.h[c] = s_a1[base + off[c]];
-                b.l[c] = s_a1[base + off[c] + 2 * A1P];
-            }
-            b.h8 = s_a1h[2 * base + off8];
-            b.l8 = s_a1h[2 * base + off8 + 4 * A1P];
-            f32x4 va, vb;
-            conv2_mfma(wa, wb, b, ba, bb, &va, &vb);
-            if (p < F2N) {
-                const bool in = r2 >= vy0 && r2 < vy1 && c2 >= vx0 && c2 < vx1;
-                va = in ? relu4(va) : splat4(0.f);
-                vb = in ? relu4(vb) : splat4(0.f);
-                uint2 hi, lo;
-                split4(va, &hi, &lo);
-                s_a2h[2 * split_entry<A2P, F2J>(g >> 1, 0, r2, c2) + (g & 1)] = hi;
-                s_a2h[2 * split_entry<A2P, F2J>(g >> 1, 1, r2, c2) + (g & 1)] = lo;
-                split4(vb, &hi, &lo);
-                s_a2h[2 * split_entry<A2P, F2J>(2 + (g >> 1), 0, r2, c2) + (g & 1)] = hi;
-                s_a2h[2 * split_entry<A2P, F2J>(2 + (g >> 1), 1, r2, c2) + (g & 1)] = lo;
-            }
-        }
-    }
-    __syncthreads();
-
-    // D. conv3 (32 -> 32) + head: wave w < 4 takes 16 grid positions (w & 1)
-    //    and one 16-channel block (w >> 1); the two blocks' head sums meet in LDS
-    if (wave < 4) {
-        const int nt = wave & 1, mb = wave >> 1;
-        const int p = 16 * nt + m, r3 = p >> 3, c3 = p & 7;
-        const W3 w = conv3_a(wp3, lane, 16 * mb);
-        B3 b;
-#pragma unroll
-        for (int t = 0; t < 9; t++) {
-            const int e = split_entry<A2P, F2J>(g, 0, 2 * r3 + t / 3, 2 * c3 + t % 3);
-            b.h[t] = s_u[e];
-            b.l[t] = s_u[e + 2 * A2P];
-        }
-        const f32x4 v = relu4(conv3_mfma(w, b, conv_bias(prm, P_B3 + 16 * mb, lane)));
-        const float part = head16(v, prm, 16 * mb, lane);
-        if (g == 0) s_head[mb][p] = part;
-    }
-    __syncthreads();
-    if (tid < 32) {
-        const int r3 = tid >> 3, c3 = tid & 7;
-        const int gy = Y3 + r3, gx = X3 + c3;
-        if (gy < im.h4 && gx < im.w4) z[im.px4 + (int64_t)gy * im.w4 + gx] = (s_head[0][tid] + s_head[1][tid]) + bf(prm[P_B4]);
     }
 }
+
+// stage fetched dwords as float16 (I - 128) / 128, zero outside the level
+__device__ __forceinline__ void fused_stage(uint8_t *s_in, const CnnImg &im, const FTile &f, const int *rr,
+                                            const int *jj, const uint32_t *v) {
+    const int Y0 = 8 * f.Y3 - 7, XS = 8 * f.X3 - 8;
+    const bool interior = Y0 >= 0 && Y0 + F0H <= im.h3 && XS >= 0 && XS + 4 * F0D <= im.w3;
+#pragma unroll
+    for (int k = 0; k < F_LD; k++) {
+        if (rr[k] >= F0H) continue;
+        uint2 x = x_h4(v[k]);
+        if (!interior) {
+            const int gy = Y0 + rr[k], gx = XS + 4 * jj[k];
+            const bool row = gy >= 0 && gy < im.h3 && gx >= 0;
+            const int nv = row ? min(max(im.w3 - gx, 0), 4) : 0;       // valid columns of the dword
+            x.x &= nv >= 2 ? 0xFFFFFFFFu : (nv == 1 ? 0xFFFFu : 0u);
+            x.y &= nv >= 4 ? 0xFFFFFFFFu : (nv == 3 ? 0xFFFFu : 0u);
+        }
+        *(uint2 *)(s_in + rr[k] * F0S + 8 * jj[k]) = x;
+    }
+}
+
+// bit r set for the window rows r in [lo, hi)
+__device__ __forceinline__ uint32_t row_bits(int lo, int hi) {
+    lo = max(lo, 0);
+    return hi > lo ? (hi >= 32 ? 0xFFFFFFFFu : (1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
+}
+
+__global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kernel(
+    const CnnImg *__restrict__ imgs, const int32_t *__restrict__ pre_tiles, int n, int n_tiles,
+    const uint8_t *__restrict__ pyr, const uint16_t *__restrict__ prm, const uint16_t *__restrict__ wp1,
+    const uint16_t *__restrict__ wp2, const uint16_t *__restrict__ wp3, float *__restrict__ z) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_in[F0H * F0S];
+    __shared__ uint4 s_a1[2 * A1E];
+    __shared__ uint4 s_a2[4 * A2E];
+    __shared__ float s_head[2][16 * F_NT];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int m = lane & 15, g = lane >> 4;
+
+    // this block's tiles: XCD x = block % 8 owns a contiguous eighth of the
+    // tiles, which its blocks take in turn (neighbouring tiles share halo
+    // rows in that XCD's L2)
+    const int x = blockIdx.x % N_XCD, nbx = ((int)gridDim.x - x + N_XCD - 1) / N_XCD, lb = blockIdx.x / N_XCD;
+    const int t_lo = (int)((int64_t)n_tiles * x / N_XCD), t_hi = (int)((int64_t)n_tiles * (x + 1) / N_XCD);
+    const int first = t_lo + lb;
+    const int K = first < t_hi ? (t_hi - first + nbx - 1) / nbx : 0;
+    if (K == 0) return;
+    auto tile_at = [&](int k) { return first + k * nbx; };
+
+    // staging slots of this thread (tile independent)
+    int rr[F_LD], jj[F_LD];
+#pragma unroll
+    for (int k = 0; k < F_LD; k++) {
+        const int d = tid + F_THREADS * k;
+        rr[k] = d / F0D;                                  // >= F0H: no slot
+        jj[k] = d - rr[k] * F0D;
+    }
+
+    // weights held for the whole walk
+    const uint2 w1 = conv1_a(wp1, lane);
+    const f32x4 b1 = conv_bias(prm, P_B1, lane);
+    const W2 w2a = conv2_a(wp2, lane, 0), w2b = conv2_a(wp2, lane, 16);
+    const f32x4 b2a = conv_bias(prm, P_B2, lane), b2b = conv_bias(prm, P_B2 + 16, lane);
+    const int mb3 = wv & 1;
+    const W3 w3 = conv3_a(wp3, lane, 16 * mb3);
+    const f32x4 b3 = conv_bias(prm, P_B3 + 16 * mb3, lane);
+    const f32x4 hw = head_w(prm, 16 * mb3, lane);
+    const float b4 = bf(prm[P_B4]);
+
+    // lane-constant LDS byte offsets (units add compile-time strides)
+    // conv1: parity wave & 1, rows from r1b; column C1 = 2 m + parity; lane
+    // group g reads tap row min(g, 2)
+    const int par1 = wv & 1, r1b = wv < 2 ? 0 : F_R1A;
+    const int in_off = (2 * r1b + min(g, 2)) * F0S + 8 * m + 4 * par1;
+    const int a1_woff = ((par1 * F1H + r1b) * F1J + m) * 32 + 8 * g;
+    // conv2: rows wave + 4 i; lane m is output column c2 = 2 (m & 7) + (m >> 3);
+    // chunk c, lane group g reads tap 2 c + g / 2 (channels 8 (g & 1) ..),
+    // tap 8 channels 4 g ..
+    const int c2 = 2 * (m & 7) + (m >> 3);
+    int a1_roff[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const int t = 2 * c + (g >> 1), ky = t / 3, kx = t % 3;
+        const int C1 = 2 * c2 + kx;
+        a1_roff[c] = (((C1 & 1) * F1H + 2 * wv + ky) * F1J + (C1 >> 1)) * 32 + 16 * (g & 1);
+    }
+    const int a1_roff8 = ((2 * wv + 2) * F1J + c2 + 1) * 32 + 8 * g;
+    const int a2_woff = (((m >> 3) * F2H + wv) * F2J + (m & 7)) * 64 + 8 * g;
+    // conv3: position groups (wave >> 1) + 2 i, positions 16 group + m
+    // (valid < 42) at (r3, c3); tap (0, 0) here, the others add constants
+    int a2_roff[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const int p3 = min(16 * ((wv >> 1) + 2 * i) + m, F_NPOS - 1), r3 = p3 / F3W, c3 = p3 - r3 * F3W;
+        a2_roff[i] = ((2 * r3) * F2J + c3) * 64 + 16 * g;
+    }
+
+    uint8_t *const a1b = (uint8_t *)s_a1;
+    uint8_t *const a2b = (uint8_t *)s_a2;
+
+    int cursor = find_image(pre_tiles, n, first);
+    FTile f_prev{0, 0, 0}, f_cur = fused_tile(imgs, pre_tiles, n, tile_at(0), cursor);
+    FTile f_next = K > 1 ? fused_tile(imgs, pre_tiles, n, tile_at(1), cursor) : f_cur;
+    uint32_t pf[F_LD];
+    {
+        const CnnImg im = imgs[f_cur.img];
+        fused_fetch(pyr, im, f_cur, rr, jj, pf);
+        fused_stage(s_in, im, f_cur, rr, jj, pf);
+    }
+    if (K > 1) fused_fetch(pyr, imgs[f_next.img], f_next, rr, jj, pf);
+    __syncthreads();
+
+    for (int k = 0; k <= K; k++) {
+        // phase X: conv1 of tile k (input -> conv1 planes) and conv3 + head
+        // of tile k - 1 (conv2 planes -> head sums)
+        if (k < K) {
+            const CnnImg im = imgs[f_cur.img];
+            const int Y1 = 4 * f_cur.Y3 - 3, X1 = 4 * f_cur.X3 - 3;
+            const uint32_t rows = row_bits(-Y1, im.h1 - Y1) >> r1b;       // bit i: row r1b + i inside
+            const bool col_ok = X1 + 2 * m + par1 >= 0 && X1 + 2 * m + par1 < im.w1;
+            auto run = [&](auto masked, int i0, auto n_units) {
+                constexpr int NU = decltype(n_units)::value;
+                uint2 xb[NU];
+#pragma unroll
+                for (int j = 0; j < NU; j++) {
+                    const uint8_t *src = s_in + in_off + (i0 + j) * 2 * F0S;
+                    xb[j] = make_uint2(*(const uint32_t *)src, *(const uint32_t *)(src + 4));
+                }
+#pragma unroll
+                for (int j = 0; j < NU; j++) {
+                    uint2 o = relu_h4(mfma16(w1, xb[j], b1));
+                    if constexpr (decltype(masked)::value) {
+                        const bool ok = col_ok && ((rows >> (i0 + j)) & 1u);
+                        o.x = ok ? o.x : 0u;
+                        o.y = ok ? o.y : 0u;
+                    }
+                    *(uint2 *)(a1b + a1_woff + (i0 + j) * F1J * 32) = o;
+                }
+            };
+            using T6 = std::integral_constant<int, 6>;
+            using T3 = std::integral_constant<int, 3>;
+            const bool inside = Y1 >= 0 && Y1 + F1H <= im.h1 && X1 >= 0 && X1 + F1W <= im.w1;
+            if (inside) {
+                run(std::false_type{}, 0, T6{});
+                run(std::false_type{}, 6, T6{});
+                if (wv >= 2) run(std::false_type{}, 12, T3{});
+            } else {
+                run(std::true_type{}, 0, T6{});
+                run(std::true_type{}, 6, T6{});
+                if (wv >= 2) run(std::true_type{}, 12, T3{});
+            }
+        }
+        if (k > 0) {
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                if (i == 1 && wv >= 2) break;                              // uniform
+                uint4 bt[9];
+#pragma unroll
+                for (int t = 0; t < 9; t++) {
+                    const int ky = t / 3, kx = t % 3;
+                    bt[t] = *(const uint4 *)(a2b + a2_roff[i] + (((kx & 1) * F2H + ky) * F2J + (kx >> 1)) * 64);
+                }
+                f32x4 acc = b3;
+#pragma unroll
+                for (int t = 0; t < 9; t++) acc = mfma32(w3.t[t], bt[t], acc);
+                const float part = head16(relu4(acc), hw);
+                const int p = 16 * ((wv >> 1) + 2 * i) + m;
+                if (g == 0 && p < F_NPOS) s_head[mb3][p] = part;
+            }
+        }
+        __syncthreads();
+        // phase Y: staging of tile k + 1 and the fetch of tile k + 2, logits
+        // of tile k - 1, conv2 of tile k (conv1 planes -> conv2 planes)
+        FTile f_new = f_next;
+        if (k + 1 < K) {
+            fused_stage(s_in, imgs[f_next.img], f_next, rr, jj, pf);
+            if (k + 2 < K) {
+                f_new = fused_tile(imgs, pre_tiles, n, tile_at(k + 2), cursor);
+                fused_fetch(pyr, imgs[f_new.img], f_new, rr, jj, pf);
+            }
+        }
+        if (k > 0 && tid < F_NPOS) {
+            const CnnImg im = imgs[f_prev.img];
+            const int gy = f_prev.Y3 + tid / F3W, gx = f_prev.X3 + tid % F3W;
+            if (gy < im.h4 && gx < im.w4) z[im.px4 + (int64_t)gy * im.w4 + gx] = (s_head[0][tid] + s_head[1][tid]) + b4;
+        }
+        if (k < K) {
+            const CnnImg im = imgs[f_cur.img];
+            const int Y2 = 2 * f_cur.Y3 - 1, X2 = 2 * f_cur.X3 - 1;
+            const uint32_t rows = row_bits(-Y2, im.h2 - Y2);
+            const bool col_ok = X2 + c2 >= 0 && X2 + c2 < im.w2;
+            const bool inside = Y2 >= 0 && Y2 + F2H <= im.h2 && X2 >= 0 && X2 + F2W <= im.w2;
+            auto unit = [&](auto masked, int i) {
+                B2 b;
+#pragma unroll
+                for (int c = 0; c < 4; c++) b.c[c] = *(const uint4 *)(a1b + a1_roff[c] + i * 8 * F1J * 32);
+                b.t8 = *(const uint2 *)(a1b + a1_roff8 + i * 8 * F1J * 32);
+                uint2 oa = relu_h4(conv2_mfma(w2a, b, b2a));
+                uint2 ob = relu_h4(conv2_mfma(w2b, b, b2b));
+                if constexpr (decltype(masked)::value) {
+                    const bool ok = col_ok && ((rows >> (wv + 4 * i)) & 1u);
+                    oa.x = ok ? oa.x : 0u;
+                    oa.y = ok ? oa.y : 0u;
+                    ob.x = ok ? ob.x : 0u;
+                    ob.y = ok ? ob.y : 0u;
+                }
+                *(uint2 *)(a2b + a2_woff + i * 4 * F2J * 64) = oa;
+                *(uint2 *)(a2b + a2_woff + i * 4 * F2J * 64 + 32) = ob;
+            };
+            // rows wave + 4 i: three for every wave, a fourth (row 12) for wave 0
+            if (inside) {
+#pragma unroll
+                for (int i = 0; i < 3; i++) unit(std::false_type{}, i);
+                if (wv == 0) unit(std::false_type{}, 3);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; i++) unit(std::true_type{}, i);
+                if (wv == 0) unit(std::true_type{}, 3);
+            }
+        }
+        f_prev = f_cur;
+        f_cur = f_next;
+        f_next = f_new;
+        __syncthreads();
+    }
+}
+
+}  // namespace inf
 
 __global__ void cnn_cells_kernel(const CnnImg *__restrict__ imgs, const int32_t *__restrict__ pre_cells, int n,
                                  int64_t total, const float *__restrict__ z, float thresh,
@@ -820,7 +1081,7 @@ int32_t cnn_plan_check(const vsfe_batch *b) {
         st2 += (w2 * h2 + 15) / 16;
         st4 += (w4 * h4 + 15) / 16;
         sc += (int64_t)im.lv[0].ncx * im.lv[0].ncy;
-        stf += ((w4 + F3W - 1) / F3W) * ((h4 + F3H - 1) / F3H);
+        stf += ((w4 + inf::F3W - 1) / inf::F3W) * ((h4 + inf::F3H - 1) / inf::F3H);
     }
     const int64_t lim = (int64_t)1 << 31;
     // the layer arrays are also indexed as (pixel * 32 + channel) in 64 bits;
@@ -878,7 +1139,7 @@ int32_t cnn_setup(vsfe_batch *b) {
         st4 += ((int64_t)c.w4 * c.h4 + 15) / 16;
         sc += (int64_t)c.ncx0 * c.ncy0;
         st1 += ((int64_t)c.w1 * c.h1 + 15) / 16;
-        stf += (int64_t)((c.w4 + F3W - 1) / F3W) * ((c.h4 + F3H - 1) / F3H);
+        stf += (int64_t)((c.w4 + inf::F3W - 1) / inf::F3W) * ((c.h4 + inf::F3H - 1) / inf::F3H);
     }
     pre1[n] = (int32_t)s1;
     pre2[n] = (int32_t)s2;
@@ -902,6 +1163,12 @@ int32_t cnn_setup(vsfe_batch *b) {
     P->off_wp2 = at;
     at = align256(at + 32 * 9 * 16 * 2);
     P->off_wp3 = at;
+    at = align256(at + 32 * 9 * 32 * 2);
+    P->off_hp1 = at;
+    at = align256(at + 16 * 4 * 4 * 2);
+    P->off_hp2 = at;
+    at = align256(at + 32 * 9 * 16 * 2);
+    P->off_hp3 = at;
     at = align256(at + 32 * 9 * 32 * 2);
     P->off_a1 = at;
     at = align256(at + s1 * 16 * 4);
@@ -961,16 +1228,19 @@ static int32_t run_forward(const vsfe_batch *b, const CnnPlan *P, const uint8_t 
     const int n = P->n;
     const int32_t *pre = P->d_pre;
     uint16_t *wp2 = (uint16_t *)(ws + P->off_wp2), *wp3 = (uint16_t *)(ws + P->off_wp3);
+    uint16_t *hp1 = (uint16_t *)(ws + P->off_hp1), *hp2 = (uint16_t *)(ws + P->off_hp2),
+             *hp3 = (uint16_t *)(ws + P->off_hp3);
     float *a1 = (float *)(ws + P->off_a1), *a2 = (float *)(ws + P->off_a2), *a3 = (float *)(ws + P->off_a3);
-    hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, prm, wp2, wp3);
+    hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, prm, wp2, wp3, hp1, hp2,
+                       hp3);
     if (P->t1 > 0)
-        hipLaunchKernelGGL(cnn_conv1_kernel, dim3((unsigned)((P->t1 + 3) / 4)), dim3(256), 0, st, P->d_img,
+        hipLaunchKernelGGL(tr::cnn_conv1_kernel, dim3((unsigned)((P->t1 + 3) / 4)), dim3(256), 0, st, P->d_img,
                            pre + 6 * (n + 1), n, P->t1, pyr, prm, a1);
     if (P->t2 > 0)
-        hipLaunchKernelGGL(cnn_conv2_kernel, dim3((unsigned)((P->t2 + 3) / 4)), dim3(256), 0, st, P->d_img,
+        hipLaunchKernelGGL(tr::cnn_conv2_kernel, dim3((unsigned)((P->t2 + 3) / 4)), dim3(256), 0, st, P->d_img,
                            pre + 3 * (n + 1), n, P->t2, a1, a2, wp2, prm);
     if (P->t4 > 0)
-        hipLaunchKernelGGL(cnn_conv3_kernel, dim3((unsigned)((P->t4 + 3) / 4)), dim3(256), 0, st, P->d_img,
+        hipLaunchKernelGGL(tr::cnn_conv3_kernel, dim3((unsigned)((P->t4 + 3) / 4)), dim3(256), 0, st, P->d_img,
                            pre + 4 * (n + 1), n, P->t4, a2, a3, wp3, prm, z);
     (void)b;
     return check_launch("cnn forward");
@@ -1008,10 +1278,28 @@ int32_t cnn_propose(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *pyr
     hipStream_t st = (hipStream_t)stream;
     uint8_t *ws = (uint8_t *)workspace;
     uint16_t *wp2 = (uint16_t *)(ws + P->off_wp2), *wp3 = (uint16_t *)(ws + P->off_wp3);
-    hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, params_bf16, wp2, wp3);
-    if (P->tf > 0)
-        hipLaunchKernelGGL(cnn_fused_fwd_kernel, dim3((unsigned)P->tf), dim3(F_THREADS), 0, st, P->d_img,
-                           P->d_pre + 7 * (P->n + 1), P->n, pyr, params_bf16, wp2, wp3, grid_logits);
+    uint16_t *hp1 = (uint16_t *)(ws + P->off_hp1), *hp2 = (uint16_t *)(ws + P->off_hp2),
+             *hp3 = (uint16_t *)(ws + P->off_hp3);
+    hipLaunchKernelGGL(cnn_pack_kernel, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, params_bf16, wp2, wp3,
+                       hp1, hp2, hp3);
+    if (P->tf > 0) {
+        // persistent: a multiple of 8 blocks (one tile range per XCD), at
+        // most as many as are resident at once
+        static const int64_t resident = [] {
+            int dev = 0, n_cu = 0, per_cu = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, inf::cnn_fused_fwd_kernel, inf::F_THREADS, 0) !=
+                    hipSuccess ||
+                n_cu < 1 || per_cu < 1)
+                return (int64_t)256 * inf::F_BLOCKS_PER_CU;
+            return (int64_t)n_cu * per_cu;
+        }();
+        const int64_t per_xcd = std::max<int64_t>(1, std::min(resident / N_XCD, (P->tf + N_XCD - 1) / N_XCD));
+        hipLaunchKernelGGL(inf::cnn_fused_fwd_kernel, dim3((unsigned)(per_xcd * N_XCD)), dim3(inf::F_THREADS), 0, st,
+                           P->d_img, P->d_pre + 7 * (P->n + 1), P->n, (int)P->tf, pyr, params_bf16, hp1, hp2, hp3,
+                           grid_logits);
+    }
     rc = check_launch("cnn_propose (forward)");
     if (rc) return rc;
     if (P->cells > 0)

@@ -1,11 +1,12 @@
 """GPU parity of the learned cell proposer with its oracle.
 
 The network evaluated is the one with bfloat16-valued weights.  Its GPU
-logits (bfloat16 matrix products, float32 sums, activations carried as
-bfloat16 value + remainder pairs) must match the oracle's float64 forward
-of the same weights with unrounded activations (a float32-or-better CPU
-forward) within 1e-2 absolute, for random and for the packaged trained
-networks; cell logits and masks are exact functions of the grid logits;
+logits must match the oracle's float64 forward of the same weights with
+unrounded activations (a float32-or-better CPU forward) within 1e-2
+absolute, for random and for the packaged trained networks, both from the
+inference kernel (float16 activations) and from the training forward
+(bfloat16 value + remainder pairs, within 1e-3); cell logits and masks are
+exact functions of the grid logits;
 every gradient entry and the loss match the float64 oracle backward to a
 stated tolerance; the gated exact path matches the oracle run on the
 GPU's mask bit for bit, also for the benchmark's 1080p learned leg.
@@ -28,6 +29,7 @@ pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 WEIGHTS = os.path.join(ROOT, "paper_2410_04090_amd", "weights")
 LOGIT_TOL = 1e-2            # absolute, against the float64 forward of the same weights
+TRAIN_LOGIT_TOL = 1e-3      # the training forward (value + remainder pairs), same reference
 GRAD_RTOL = 1e-3            # per gradient entry, relative to the entry
 GRAD_ATOL = 1e-4            # per gradient entry, relative to the layer's largest entry
 
@@ -165,10 +167,12 @@ def test_propose_cells_and_mask(torch_mod):
         fe.close()
 
 
-def test_fused_inference_equals_layerwise_forward(torch_mod):
-    """cnn_propose (one fused kernel per 8 x 8 tile, activations in LDS) gives
-    bit-identical grid logits to cnn_forward (layer by layer through HBM), and
-    both match the oracle; sizes include tiles cut by every border."""
+def test_fused_inference_and_training_forward_match_oracle(torch_mod):
+    """cnn_propose (the persistent fused kernel, float16 activations in LDS)
+    and cnn_forward (layer by layer through HBM, bfloat16 value + remainder
+    pairs) both match the float64 forward: the inference logits within 1e-2,
+    the training logits within 1e-3; sizes include tiles cut by every
+    border and an image smaller than one tile."""
     torch = torch_mod
     imgs = images_mixed() + [scenes.random_image(4004, 61, 47), scenes.mono_image(4005, 203, 333, 40)]
     p = Params()
@@ -186,12 +190,14 @@ def test_fused_inference_equals_layerwise_forward(torch_mod):
                          fe.status)
         torch.cuda.synchronize()
         z_fused = fe.grid_logits.cpu().numpy()
-        assert np.array_equal(z_fwd.view(np.uint32), z_fused.view(np.uint32))
+        assert np.isfinite(z_fused).all()
         for i, img in enumerate(imgs):
             ref, _ = ocnn.forward(oracle.pyramid(img, 4)[3], theta, bf16=False)
-            err = np.abs(grid_of(fe, z_fused, i) - ref).max()
-            say("image", i, img.shape, "fused max |dz| vs float64 forward =", err)
-            assert err <= LOGIT_TOL
+            e_inf = np.abs(grid_of(fe, z_fused, i) - ref).max()
+            e_tr = np.abs(grid_of(fe, z_fwd, i) - ref).max()
+            say("image", i, img.shape, "max |dz| vs float64 forward: inference", e_inf, "training", e_tr)
+            assert e_inf <= LOGIT_TOL
+            assert e_tr <= TRAIN_LOGIT_TOL
     finally:
         fe.close()
 
