@@ -564,8 +564,12 @@ constexpr int F1J = 16, F2J = 8;                         // column pairs per pla
 static_assert(2 * F1J == F1W + 1 && 2 * F2J == F2W + 1, "one pad column per plane");
 constexpr int F0D = 17;                                  // input dwords per row (68 columns)
 constexpr int F0S = 8 * F0D;                             // staged row stride (bytes, float16)
-constexpr int A1E = 2 * F1H * F1J;                       // conv1 entries (864) of 32 bytes
-constexpr int A2E = 2 * F2H * F2J;                       // conv2 entries (208) of 64 bytes
+// conv1 planes: row = 2 halves (8 channels) x 16 pairs of 16 bytes, so the
+// 16 lanes of a K slice read 16 consecutive chunks; conv2 planes: row = 4
+// quarters x 8 pairs of 16 bytes plus 64 bytes of padding, so that the two
+// grid rows one conv3 tile reads (conv2 rows 2 apart) fall on disjoint banks
+constexpr int RS1 = 2 * F1J * 16, RS2 = 4 * F2J * 16 + 64;     // row strides (bytes)
+constexpr int A1B = 2 * F1H * RS1, A2B = 2 * F2H * RS2;  // plane pairs (bytes)
 constexpr int F_WAVES = 4, F_THREADS = 64 * F_WAVES;
 constexpr int F_LD = (F0H * F0D + F_THREADS - 1) / F_THREADS;   // input dwords per thread (4)
 constexpr int F_NPOS = F3H * F3W;                        // 42 grid positions
@@ -638,8 +642,8 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
     const uint8_t *__restrict__ pyr, const uint16_t *__restrict__ prm, const uint16_t *__restrict__ wp1,
     const uint16_t *__restrict__ wp2, const uint16_t *__restrict__ wp3, float *__restrict__ z) {
     __shared__ __attribute__((aligned(16))) uint8_t s_in[F0H * F0S];
-    __shared__ uint4 s_a1[2 * A1E];
-    __shared__ uint4 s_a2[4 * A2E];
+    __shared__ uint4 s_a1[A1B / 16];
+    __shared__ uint4 s_a2[A2B / 16];
     __shared__ float s_head[2][16 * F_NT];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -680,27 +684,27 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
     // group g reads tap row min(g, 2)
     const int par1 = wv & 1, r1b = wv < 2 ? 0 : F_R1A;
     const int in_off = (2 * r1b + min(g, 2)) * F0S + 8 * m + 4 * par1;
-    const int a1_woff = ((par1 * F1H + r1b) * F1J + m) * 32 + 8 * g;
-    // conv2: rows wave + 4 i; lane m is output column c2 = 2 (m & 7) + (m >> 3);
-    // chunk c, lane group g reads tap 2 c + g / 2 (channels 8 (g & 1) ..),
-    // tap 8 channels 4 g ..
-    const int c2 = 2 * (m & 7) + (m >> 3);
+    const int a1_woff = (par1 * F1H + r1b) * RS1 + (g >> 1) * 16 * F1J + 16 * m + 8 * (g & 1);
+    // conv2: rows wave + 4 i; lane m is output column m (15 is the pad
+    // column); chunk c, lane group g reads tap 2 c + g / 2, channel half
+    // g & 1 (tap 8: channels 4 g ..)
     int a1_roff[4];
 #pragma unroll
     for (int c = 0; c < 4; c++) {
         const int t = 2 * c + (g >> 1), ky = t / 3, kx = t % 3;
-        const int C1 = 2 * c2 + kx;
-        a1_roff[c] = (((C1 & 1) * F1H + 2 * wv + ky) * F1J + (C1 >> 1)) * 32 + 16 * (g & 1);
+        a1_roff[c] = ((kx & 1) * F1H + 2 * wv + ky) * RS1 + (g & 1) * 16 * F1J + 16 * (m + (kx >> 1));
     }
-    const int a1_roff8 = ((2 * wv + 2) * F1J + c2 + 1) * 32 + 8 * g;
-    const int a2_woff = (((m >> 3) * F2H + wv) * F2J + (m & 7)) * 64 + 8 * g;
-    // conv3: position groups (wave >> 1) + 2 i, positions 16 group + m
-    // (valid < 42) at (r3, c3); tap (0, 0) here, the others add constants
+    const int a1_roff8 = (2 * wv + 2) * RS1 + (g >> 1) * 16 * F1J + 16 * (m + 1) + 8 * (g & 1);
+    // output column m: parity m & 1, pair m >> 1, channel quarter 2 mb + g / 2
+    const int a2_woff = ((m & 1) * F2H + wv) * RS2 + (g >> 1) * 16 * F2J + 16 * (m >> 1) + 8 * (g & 1);
+    // conv3: unit u3 = (wave >> 1) + 2 i covers grid rows 2 u3, 2 u3 + 1 of
+    // the tile, lane m at (r3, c3) = (2 u3 + m / 8, m % 8) (c3 = 7 is not a
+    // position); tap (0, 0) here, the others add constants
     int a2_roff[2];
 #pragma unroll
     for (int i = 0; i < 2; i++) {
-        const int p3 = min(16 * ((wv >> 1) + 2 * i) + m, F_NPOS - 1), r3 = p3 / F3W, c3 = p3 - r3 * F3W;
-        a2_roff[i] = ((2 * r3) * F2J + c3) * 64 + 16 * g;
+        const int r3 = 2 * ((wv >> 1) + 2 * i) + (m >> 3), c3 = m & 7;
+        a2_roff[i] = (2 * r3) * RS2 + g * 16 * F2J + 16 * c3;
     }
 
     uint8_t *const a1b = (uint8_t *)s_a1;
@@ -742,7 +746,7 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
                         o.x = ok ? o.x : 0u;
                         o.y = ok ? o.y : 0u;
                     }
-                    *(uint2 *)(a1b + a1_woff + (i0 + j) * F1J * 32) = o;
+                    *(uint2 *)(a1b + a1_woff + (i0 + j) * RS1) = o;
                 }
             };
             using T6 = std::integral_constant<int, 6>;
@@ -766,14 +770,14 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
 #pragma unroll
                 for (int t = 0; t < 9; t++) {
                     const int ky = t / 3, kx = t % 3;
-                    bt[t] = *(const uint4 *)(a2b + a2_roff[i] + (((kx & 1) * F2H + ky) * F2J + (kx >> 1)) * 64);
+                    bt[t] = *(const uint4 *)(a2b + a2_roff[i] + ((kx & 1) * F2H + ky) * RS2 + 16 * (kx >> 1));
                 }
                 f32x4 acc = b3;
 #pragma unroll
                 for (int t = 0; t < 9; t++) acc = mfma32(w3.t[t], bt[t], acc);
                 const float part = head16(relu4(acc), hw);
-                const int p = 16 * ((wv >> 1) + 2 * i) + m;
-                if (g == 0 && p < F_NPOS) s_head[mb3][p] = part;
+                const int r3 = 2 * ((wv >> 1) + 2 * i) + (m >> 3), c3 = m & 7;
+                if (g == 0 && c3 < F3W) s_head[mb3][r3 * F3W + c3] = part;
             }
         }
         __syncthreads();
@@ -796,13 +800,13 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
             const CnnImg im = imgs[f_cur.img];
             const int Y2 = 2 * f_cur.Y3 - 1, X2 = 2 * f_cur.X3 - 1;
             const uint32_t rows = row_bits(-Y2, im.h2 - Y2);
-            const bool col_ok = X2 + c2 >= 0 && X2 + c2 < im.w2;
+            const bool col_ok = X2 + m >= 0 && X2 + m < im.w2;
             const bool inside = Y2 >= 0 && Y2 + F2H <= im.h2 && X2 >= 0 && X2 + F2W <= im.w2;
             auto unit = [&](auto masked, int i) {
                 B2 b;
 #pragma unroll
-                for (int c = 0; c < 4; c++) b.c[c] = *(const uint4 *)(a1b + a1_roff[c] + i * 8 * F1J * 32);
-                b.t8 = *(const uint2 *)(a1b + a1_roff8 + i * 8 * F1J * 32);
+                for (int c = 0; c < 4; c++) b.c[c] = *(const uint4 *)(a1b + a1_roff[c] + i * 8 * RS1);
+                b.t8 = *(const uint2 *)(a1b + a1_roff8 + i * 8 * RS1);
                 uint2 oa = relu_h4(conv2_mfma(w2a, b, b2a));
                 uint2 ob = relu_h4(conv2_mfma(w2b, b, b2b));
                 if constexpr (decltype(masked)::value) {
@@ -812,8 +816,8 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
                     ob.x = ok ? ob.x : 0u;
                     ob.y = ok ? ob.y : 0u;
                 }
-                *(uint2 *)(a2b + a2_woff + i * 4 * F2J * 64) = oa;
-                *(uint2 *)(a2b + a2_woff + i * 4 * F2J * 64 + 32) = ob;
+                *(uint2 *)(a2b + a2_woff + i * 4 * RS2) = oa;
+                *(uint2 *)(a2b + a2_woff + i * 4 * RS2 + 2 * 16 * F2J) = ob;
             };
             // rows wave + 4 i: three for every wave, a fourth (row 12) for wave 0
             if (inside) {
