@@ -249,9 +249,8 @@ struct B3 {
     uint4 h[9], l[9];
 };
 
-// conv2 on the pair chains of both 16-channel blocks; the order of the
-// products (hi chain from the bias, lo chain from zero, tap by tap, then
-// hi + lo) is the same in the fused and layer-by-layer kernels
+// conv2 on the pair chains of both 16-channel blocks (hi chain from the
+// bias, lo chain from zero, tap by tap, then hi + lo)
 __device__ __forceinline__ void conv2_mfma(const W2 &wa, const W2 &wb, const B2 &b, f32x4 bias_a, f32x4 bias_b,
                                            f32x4 *va, f32x4 *vb) {
     f32x4 ah = bias_a, bh = bias_b, al = splat4(0.f), bl = splat4(0.f);
@@ -266,8 +265,8 @@ __device__ __forceinline__ void conv2_mfma(const W2 &wa, const W2 &wb, const B2 
     bh = mfma16(as_i16x4(wb.t8), as_i16x4(b.h8), bh);
     al = mfma16(as_i16x4(wa.t8), as_i16x4(b.l8), al);
     bl = mfma16(as_i16x4(wb.t8), as_i16x4(b.l8), bl);
-    *va = ah + al;
-    *vb = bh + bl;
+    *va = mfma_settle(ah) + mfma_settle(al);
+    *vb = mfma_settle(bh) + mfma_settle(bl);
 }
 
 // conv3 of one 16-channel block
@@ -278,7 +277,7 @@ __device__ __forceinline__ f32x4 conv3_mfma(const W3 &w, const B3 &b, f32x4 bias
         h = mfma32(w.t[t], b.h[t], h);
         l = mfma32(w.t[t], b.l[t], l);
     }
-    return h + l;
+    return mfma_settle(h) + mfma_settle(l);
 }
 
 // 1x1 head partial of one 16-channel block (after ReLU): sum over the
@@ -322,7 +321,7 @@ __global__ __launch_bounds__(256) void cnn_conv1_kernel(const CnnImg *__restrict
         }
     }
     const uint2 xb = make_uint2(pk_bf(x[0], x[1]), pk_bf(x[2], x[3]));
-    const f32x4 acc = relu4(mfma16(conv1_a(prm, lane), as_i16x4(xb), conv_bias(prm, P_B1, lane)));
+    const f32x4 acc = relu4(mfma_settle(mfma16(conv1_a(prm, lane), as_i16x4(xb), conv_bias(prm, P_B1, lane))));
     if (pm < npx) *(f32x4 *)(a1 + (im.px1 + pm) * 16 + 4 * g) = acc;
 }
 
@@ -569,7 +568,11 @@ constexpr int F0S = 8 * F0D;                             // staged row stride (b
 // quarters x 8 pairs of 16 bytes plus 64 bytes of padding, so that the two
 // grid rows one conv3 tile reads (conv2 rows 2 apart) fall on disjoint banks
 constexpr int RS1 = 2 * F1J * 16, RS2 = 4 * F2J * 16 + 64;     // row strides (bytes)
-constexpr int A1B = 2 * F1H * RS1, A2B = 2 * F2H * RS2;  // plane pairs (bytes)
+// conv2's odd-column plane starts 128 bytes off the even one's banks, so the
+// even and odd output columns a conv2 unit writes do not share banks
+constexpr int P2 = F2H * RS2 + 64;                       // conv2 plane stride (bytes)
+static_assert(P2 % 256 == 128, "conv2 planes half a bank period apart");
+constexpr int A1B = 2 * F1H * RS1, A2B = 2 * P2;         // plane pairs (bytes)
 constexpr int F_WAVES = 4, F_THREADS = 64 * F_WAVES;
 constexpr int F_LD = (F0H * F0D + F_THREADS - 1) / F_THREADS;   // input dwords per thread (4)
 constexpr int F_NPOS = F3H * F3W;                        // 42 grid positions
@@ -696,7 +699,7 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
     }
     const int a1_roff8 = (2 * wv + 2) * RS1 + (g >> 1) * 16 * F1J + 16 * (m + 1) + 8 * (g & 1);
     // output column m: parity m & 1, pair m >> 1, channel quarter 2 mb + g / 2
-    const int a2_woff = ((m & 1) * F2H + wv) * RS2 + (g >> 1) * 16 * F2J + 16 * (m >> 1) + 8 * (g & 1);
+    const int a2_woff = (m & 1) * P2 + wv * RS2 + (g >> 1) * 16 * F2J + 16 * (m >> 1) + 8 * (g & 1);
     // conv3: unit u3 = (wave >> 1) + 2 i covers grid rows 2 u3, 2 u3 + 1 of
     // the tile, lane m at (r3, c3) = (2 u3 + m / 8, m % 8) (c3 = 7 is not a
     // position); tap (0, 0) here, the others add constants
@@ -740,7 +743,7 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
                 }
 #pragma unroll
                 for (int j = 0; j < NU; j++) {
-                    uint2 o = relu_h4(mfma16(w1, xb[j], b1));
+                    uint2 o = relu_h4(mfma_settle(mfma16(w1, xb[j], b1)));
                     if constexpr (decltype(masked)::value) {
                         const bool ok = col_ok && ((rows >> (i0 + j)) & 1u);
                         o.x = ok ? o.x : 0u;
@@ -770,12 +773,16 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
 #pragma unroll
                 for (int t = 0; t < 9; t++) {
                     const int ky = t / 3, kx = t % 3;
-                    bt[t] = *(const uint4 *)(a2b + a2_roff[i] + ((kx & 1) * F2H + ky) * RS2 + 16 * (kx >> 1));
+                    bt[t] = *(const uint4 *)(a2b + a2_roff[i] + (kx & 1) * P2 + ky * RS2 + 16 * (kx >> 1));
                 }
-                f32x4 acc = b3;
+                // two independent chains (taps 0-4 from the bias, 5-8 from
+                // zero) halve the dependent MFMA latency
+                f32x4 acc = b3, acc2 = splat4(0.f);
 #pragma unroll
-                for (int t = 0; t < 9; t++) acc = mfma32(w3.t[t], bt[t], acc);
-                const float part = head16(relu4(acc), hw);
+                for (int t = 0; t < 5; t++) acc = mfma32(w3.t[t], bt[t], acc);
+#pragma unroll
+                for (int t = 5; t < 9; t++) acc2 = mfma32(w3.t[t], bt[t], acc2);
+                const float part = head16(relu4(mfma_settle(acc) + mfma_settle(acc2)), hw);
                 const int r3 = 2 * ((wv >> 1) + 2 * i) + (m >> 3), c3 = m & 7;
                 if (g == 0 && c3 < F3W) s_head[mb3][r3 * F3W + c3] = part;
             }
@@ -791,10 +798,11 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
                 fused_fetch(pyr, imgs[f_new.img], f_new, rr, jj, pf);
             }
         }
-        if (k > 0 && tid < F_NPOS) {
+        const int zp = tid;
+        if (k > 0 && zp < F_NPOS) {
             const CnnImg im = imgs[f_prev.img];
-            const int gy = f_prev.Y3 + tid / F3W, gx = f_prev.X3 + tid % F3W;
-            if (gy < im.h4 && gx < im.w4) z[im.px4 + (int64_t)gy * im.w4 + gx] = (s_head[0][tid] + s_head[1][tid]) + b4;
+            const int gy = f_prev.Y3 + zp / F3W, gx = f_prev.X3 + zp % F3W;
+            if (gy < im.h4 && gx < im.w4) z[im.px4 + (int64_t)gy * im.w4 + gx] = (s_head[0][zp] + s_head[1][zp]) + b4;
         }
         if (k < K) {
             const CnnImg im = imgs[f_cur.img];
@@ -807,8 +815,8 @@ __global__ __launch_bounds__(F_THREADS, F_BLOCKS_PER_CU) void cnn_fused_fwd_kern
 #pragma unroll
                 for (int c = 0; c < 4; c++) b.c[c] = *(const uint4 *)(a1b + a1_roff[c] + i * 8 * RS1);
                 b.t8 = *(const uint2 *)(a1b + a1_roff8 + i * 8 * RS1);
-                uint2 oa = relu_h4(conv2_mfma(w2a, b, b2a));
-                uint2 ob = relu_h4(conv2_mfma(w2b, b, b2b));
+                uint2 oa = relu_h4(mfma_settle(conv2_mfma(w2a, b, b2a)));
+                uint2 ob = relu_h4(mfma_settle(conv2_mfma(w2b, b, b2b)));
                 if constexpr (decltype(masked)::value) {
                     const bool ok = col_ok && ((rows >> (wv + 4 * i)) & 1u);
                     oa.x = ok ? oa.x : 0u;

@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256, 6) void orb_kernel(const ImageDev *__restrict_
                         const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, delta);
                         const long av = (long)(((uint64_t)hi << 32) | lo);
                         const i32x4 acc = __builtin_amdgcn_mfma_i32_16x16x32_i8(av, band, i32x4{128, 128, 128, 128}, 0, 0, 0);
-                        *(uint32_t *)(HT + (16 * nt + mrow) * HT_STRIDE + 16 * mt + 4 * grp) = pack_byte1(acc);
+                        *(uint32_t *)(HT + (16 * nt + mrow) * HT_STRIDE + 16 * mt + 4 * grp) = pack_byte1(mfma_settle(acc));
                     }
                 }
                 wave_lds_fence();
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256, 6) void orb_kernel(const ImageDev *__restrict_
                         const long bv = (long)((((uint64_t)hv.y) << 32) | hv.x);
                         const i32x4 acc =
                             __builtin_amdgcn_mfma_i32_16x16x32_i8(band, bv, i32x4{32896, 32896, 32896, 32896}, 0, 0, 0);
-                        s_b[wave][((16 * nt + mrow) * B_STRIDE + 16 * mt + 4 * grp) >> 2] = pack_byte1(acc);
+                        s_b[wave][((16 * nt + mrow) * B_STRIDE + 16 * mt + 4 * grp) >> 2] = pack_byte1(mfma_settle(acc));
                     }
                 }
             } else {

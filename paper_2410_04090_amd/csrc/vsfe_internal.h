@@ -137,6 +137,18 @@ struct vsfe_batch {
 
 namespace vsfe {
 
+// A matrix-core product read by ordinary vector instructions: eight more
+// wait states between the product and its first reader than the compiler
+// inserts.  (With the VGPR-destination forms its count was measured short
+// on gfx950: float16 products read right after it were now and then stale
+// in their later output columns, varying from run to run.)  The asm takes
+// the value as an operand, so it sits between the product and its uses.
+template <typename T>
+__device__ __forceinline__ T mfma_settle(T v) {
+    asm volatile("s_nop 7" : "+v"(v));
+    return v;
+}
+
 // XCD-aware block order.  Workgroups are dispatched round-robin over the 8
 // XCDs (block b runs on XCD b % 8), each with its own L2; this maps block b
 // to work item index so that each XCD gets a contiguous range of items

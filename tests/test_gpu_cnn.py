@@ -137,6 +137,35 @@ def test_trained_network_logits_match_float64_forward(torch_mod, size, W, H, pol
         fe.close()
 
 
+def test_inference_is_deterministic(torch_mod):
+    """Three cnn_propose calls on a 1080p pair give the same logits bit for
+    bit (matrix-core products read too early differ from run to run in
+    their later output columns), and they match the float64 forward."""
+    torch = torch_mod
+    theta, _ = packaged("1920x1080")
+    imgs = list(scenes.stereo_pair(6002, 1920, 1080, 800, 128))
+    fe = make_batch(torch, imgs, Params())
+    try:
+        from paper_2410_04090_amd import vsfe
+        fe.run(describe=False)
+        w = bf16_tensor(torch, theta)
+        zs = []
+        for _ in range(3):
+            fe.grid_logits.fill_(float("nan"))
+            vsfe.cnn_propose(fe.ctx, fe.batch, fe.pyr, w, 0.0, fe.cnn_ws, fe.grid_logits, fe.cell_logits,
+                             fe.cell_mask, fe.status)
+            torch.cuda.synchronize()
+            zs.append(fe.grid_logits.cpu().numpy().copy())
+        for z in zs[1:]:
+            assert np.array_equal(zs[0].view(np.uint32), z.view(np.uint32))
+        ref, _ = ocnn.forward(oracle.pyramid(imgs[1], 4)[3], theta, bf16=False)
+        err = np.abs(grid_of(fe, zs[0], 1) - ref).max()
+        say("repeated 1080p inference: identical; max |dz| =", err)
+        assert err <= LOGIT_TOL
+    finally:
+        fe.close()
+
+
 def test_propose_cells_and_mask(torch_mod):
     torch = torch_mod
     imgs = images_mixed()[:2]
