@@ -184,6 +184,8 @@ typedef struct {
     float us[VSFE_MAX_LEVELS];         /* mean launch time of the chosen shape, microseconds */
     float us_before[VSFE_MAX_LEVELS];  /* ... of the shape the batch had before tuning */
     int32_t n_tried[VSFE_MAX_LEVELS];  /* distinct shapes timed */
+    float us_worst[VSFE_MAX_LEVELS];   /* slowest shape timed (the landscape's spread) */
+    float us_median[VSFE_MAX_LEVELS];  /* median over the shapes timed */
 } vsfe_tune_report;
 
 /* Per-level detector tile extents of a batch (host arrays of n_levels

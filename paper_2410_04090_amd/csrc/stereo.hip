@@ -1,7 +1,7 @@
 // Stereo matching along rectified rows by descriptor-distance minimisation
 // (Sec. III-3, the middle-end's stereo matcher).
 //
-// One thread per left keypoint.  Right keypoints are stored in canonical
+// 1 to 16 lanes per left keypoint.  Right keypoints are stored in canonical
 // order (level, cell row, cell column), so the candidates of a left
 // keypoint at level l and row y -- same level, |dy| <= row_band -- lie in
 // the contiguous run of cell rows floor((y - band) / c_l) ..
@@ -47,15 +47,22 @@ __global__ __launch_bounds__(256) void row_table_kernel(const ImageDev *__restri
     for (int e = lo; e <= hi; e++) tab[e] = j;
 }
 
+// G lanes per left keypoint (1, 4 or 16: more for small batches, whose
+// few keypoints leave the GPU waiting on each candidate walk): lane k scans
+// candidates start + k, + G, ... and the group keeps the least (distance,
+// |dy|, disparity, index) key, which is the ascending scan's choice with
+// strict comparisons
+template <int ST_GROUP>
 __global__ __launch_bounds__(256) void stereo_kernel(const ImageDev *__restrict__ imgs, vsfe_kp_soa kps,
                                                      const int32_t *__restrict__ kp_count,
                                                      const uint32_t *__restrict__ desc, int32_t *__restrict__ midx,
                                                      uint16_t *__restrict__ mdist, int16_t *__restrict__ mdisp,
                                                      const int32_t *__restrict__ tab, StereoArgs a) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / ST_GROUP;
+    const int k = threadIdx.x & (ST_GROUP - 1);
     const int pair = (int)(s / a.n_max);
     const int i = (int)(s - (int64_t)pair * a.n_max);
-    if (pair >= a.n_pairs) return;
+    if (pair >= a.n_pairs) return;                      // (whole groups exit together)
     const int li = 2 * pair, ri = 2 * pair + 1;
     if (i >= kp_count[li]) return;
     const int64_t lslot = imgs[li].kp_offset + i;
@@ -74,29 +81,35 @@ __global__ __launch_bounds__(256) void stereo_kernel(const ImageDev *__restrict_
     const int start = min(max(tab[rl.row_tab + cy_lo], 0), nr);
     const int end = min(max(tab[rl.row_tab + cy_hi + 1], start), nr);
 
-    int best = -1, bd = 0, bdy = 0, bdisp = 0;
-    for (int j = start; j < end; j++) {
+    // key = distance << 40 | |dy| << 32 | disparity << 16 | index (no candidate: all ones)
+    uint64_t key = ~(uint64_t)0;
+    for (int j = start + k; j < end; j += ST_GROUP) {
         const int64_t rs = rbase + j;
         int dy = (int)kps.y[rs] - y;
         dy = dy < 0 ? -dy : dy;
         if (dy > a.band) continue;
         const int dd = x0 - (int)kps.x0[rs];
         if (dd < 0 || dd > a.d_max) continue;
-        int h = 0;
+        uint32_t h = 0;
 #pragma unroll
         for (int w = 0; w < 8; w++) h += __popc(d[w] ^ desc[rs * 8 + w]);
-        if (best < 0 || h < bd || (h == bd && (dy < bdy || (dy == bdy && dd < bdisp)))) {
-            best = j;
-            bd = h;
-            bdy = dy;
-            bdisp = dd;
-        }
+        const uint64_t kj = ((uint64_t)h << 40) | ((uint64_t)dy << 32) | ((uint64_t)dd << 16) | (uint64_t)j;
+        key = kj < key ? kj : key;
     }
+#pragma unroll
+    for (int m = ST_GROUP / 2; m > 0; m >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)key, m, ST_GROUP);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(key >> 32), m, ST_GROUP);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        key = o < key ? o : key;
+    }
+    if (k != 0) return;
     const int64_t o = (int64_t)pair * a.n_max + i;
-    if (best >= 0 && bd <= a.match_th) {
-        midx[o] = best;
+    const uint32_t bd = (uint32_t)(key >> 40);
+    if (key != ~(uint64_t)0 && (int)bd <= a.match_th) {
+        midx[o] = (int32_t)(key & 0xFFFFu);
         mdist[o] = (uint16_t)bd;
-        mdisp[o] = (int16_t)bdisp;
+        mdisp[o] = (int16_t)((key >> 16) & 0xFFFFu);
     } else {
         midx[o] = -1;
         mdist[o] = 0xFFFF;
@@ -131,7 +144,16 @@ extern "C" int32_t stereo_match(const vsfe_ctx *ctx, const vsfe_batch *b, const 
                        b->d_images, *kps, kp_count, b->d_row_tab, a);
     rc = check_launch("stereo_match (row table)");
     if (rc) return rc;
-    hipLaunchKernelGGL(stereo_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       b->d_images, *kps, kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
+    if (n >= ((int64_t)1 << 27)) return fail(VSFE_ECAPACITY, "too many keypoint slots");
+    const hipStream_t st = (hipStream_t)stream;
+    if (n < 16384)
+        hipLaunchKernelGGL(stereo_kernel<16>, dim3((unsigned)((n * 16 + 255) / 256)), dim3(256), 0, st, b->d_images,
+                           *kps, kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
+    else if (n < 131072)
+        hipLaunchKernelGGL(stereo_kernel<4>, dim3((unsigned)((n * 4 + 255) / 256)), dim3(256), 0, st, b->d_images,
+                           *kps, kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
+    else
+        hipLaunchKernelGGL(stereo_kernel<1>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, b->d_images, *kps,
+                           kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
     return check_launch("stereo_match");
 }

@@ -146,6 +146,7 @@ int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *i
             }
         float best = 0.f;
         int best_k = 0;
+        std::vector<float> times;
         for (size_t k = 0; k < cand.size() && !rc; k++) {
             std::vector<DetItem> items;
             det_items_level(b, l, cand[k].first, cand[k].second, &items);
@@ -175,6 +176,7 @@ int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *i
             (void)hipEventElapsedTime(&ms, e0, e1);
             const float us = ms * 1000.f / reps;
             if (k == 0) out->us_before[l] = us;
+            times.push_back(us);
             if (k == 0 || us < best) {
                 best = us;
                 best_k = (int)k;
@@ -190,6 +192,11 @@ int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *i
         out->tile_h[l] = ny * c;
         out->us[l] = best;
         out->n_tried[l] = (int32_t)cand.size();
+        if (!times.empty()) {
+            std::sort(times.begin(), times.end());
+            out->us_worst[l] = times.back();
+            out->us_median[l] = times[times.size() / 2];
+        }
     }
     if (d_items) (void)hipFree(d_items);
     (void)hipEventDestroy(e0);

@@ -65,13 +65,15 @@ class CnnInfo(C.Structure):
 class TuneReport(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("tile_w", C.c_int32 * MAX_LEVELS), ("tile_h", C.c_int32 * MAX_LEVELS),
                 ("us", C.c_float * MAX_LEVELS), ("us_before", C.c_float * MAX_LEVELS),
-                ("n_tried", C.c_int32 * MAX_LEVELS)]
+                ("n_tried", C.c_int32 * MAX_LEVELS), ("us_worst", C.c_float * MAX_LEVELS),
+                ("us_median", C.c_float * MAX_LEVELS)]
 
     def as_dict(self):
         n = self.n_levels
         return {"tile_w": list(self.tile_w[:n]), "tile_h": list(self.tile_h[:n]),
                 "us": [round(x, 2) for x in self.us[:n]], "us_before": [round(x, 2) for x in self.us_before[:n]],
-                "n_tried": list(self.n_tried[:n])}
+                "n_tried": list(self.n_tried[:n]), "us_worst": [round(x, 2) for x in self.us_worst[:n]],
+                "us_median": [round(x, 2) for x in self.us_median[:n]]}
 
 
 EXPORTS = ["vsfe_params_default", "vsfe_params_check", "vsfe_level_geometry", "vsfe_ctx_create",
