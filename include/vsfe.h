@@ -186,6 +186,12 @@ typedef struct {
     int32_t n_tried[VSFE_MAX_LEVELS];  /* distinct shapes timed */
     float us_worst[VSFE_MAX_LEVELS];   /* slowest shape timed (the landscape's spread) */
     float us_median[VSFE_MAX_LEVELS];  /* median over the shapes timed */
+    int32_t pyr_schedule;              /* chosen pyramid schedule (VSFE_PYR_LEVELS / _TOWER) */
+    int32_t pyr_tile_w, pyr_tile_h;    /* ... and single-launch tile */
+    float pyr_us;                      /* pyramid_build time of the chosen schedule, microseconds */
+    float pyr_us_before;               /* ... of the schedule the batch had before tuning */
+    float pyr_us_worst;                /* slowest schedule timed */
+    int32_t pyr_n_tried;               /* schedules timed (0 with one level) */
 } vsfe_tune_report;
 
 /* Per-level detector tile extents of a batch (host arrays of n_levels
@@ -198,13 +204,45 @@ typedef struct {
 int32_t vsfe_batch_tiles_get(const vsfe_batch *b, int32_t *tile_w, int32_t *tile_h);
 int32_t vsfe_batch_set_tiles(vsfe_batch *b, const int32_t *tile_w, const int32_t *tile_h);
 
-/* Batching autotuner.  For every pyramid level, times fast_br_detect (no
- * cell mask) over that level of every image of the batch for each distinct
- * whole-cell tile shape that fits the detector's 128 x 32 pixel block (one
- * warm-up and `reps` timed launches each, HIP events on `stream`), keeps the
- * fastest per level and installs it as by vsfe_batch_set_tiles.  `images`
- * and `pyr` must hold the batch's data with the pyramid built; `cell_keys`
- * (n_cells entries) is overwritten.  Set-up call: synchronous, allocates a
+/* Pyramid schedule of a batch (results never depend on it):
+ *   VSFE_PYR_LEVELS  one launch per level, each level from the previous one
+ *                    in HBM;
+ *   VSFE_PYR_TOWER   one launch for all levels: a block stages a level-0
+ *                    window and builds its tile of every level in LDS, with
+ *                    the halo the smaller levels need (tile_w x tile_h is
+ *                    the owned tile at level 1);
+ *   VSFE_PYR_AUTO    (default) TOWER for batches of at most 2^26 level-0
+ *                    pixels where its plan fits, else LEVELS (measured:
+ *                    TOWER wins on small and mixed batches, where levels are
+ *                    launch- and latency-bound; LEVELS on 64 1080p pairs,
+ *                    where it streams HBM).
+ * tile_w / tile_h: 0 = default (112 x 32, or 64 x 16 when the batch has
+ * fewer than 512 blocks of 112 x 32); else 16..240 columns, a multiple
+ * of 4, and 4..64 rows.  Host only; a new tile synchronises the device and
+ * replaces the batch's plan tables, so HIP graphs captured earlier with this
+ * batch must be captured again.  Errors: EINVAL (unknown schedule, tile out
+ * of range), ECAPACITY (TOWER requested but its block does not fit; a tile
+ * that does not fit leaves the default tile planned), EHIP.
+ * pyramid_build_levels always uses one launch per level. */
+#define VSFE_PYR_AUTO   0
+#define VSFE_PYR_LEVELS 1
+#define VSFE_PYR_TOWER  2
+int32_t vsfe_batch_set_pyramid(vsfe_batch *b, int32_t schedule, int32_t tile_w, int32_t tile_h);
+/* The schedule pyramid_build will use (LEVELS or TOWER) and the planned
+ * single-launch tile. */
+int32_t vsfe_batch_pyramid_get(const vsfe_batch *b, int32_t *schedule, int32_t *tile_w, int32_t *tile_h);
+
+/* Batching autotuner.  First times pyramid_build under the batch's current
+ * schedule, one launch per level and single-launch tiles from 48 x 8 to
+ * 240 x 32 (those whose block fits), and installs the fastest as by
+ * vsfe_batch_set_pyramid; `pyr` is rewritten with the same bytes.  Then,
+ * for every pyramid level, times fast_br_detect (no cell mask) over that
+ * level of every image of the batch for each distinct whole-cell tile shape
+ * that fits the detector's 128 x 32 pixel block (one warm-up and `reps`
+ * timed launches each, HIP events on `stream`), keeps the fastest per level
+ * and installs it as by vsfe_batch_set_tiles.  `images` and `pyr` must hold
+ * the batch's data with the pyramid built; `cell_keys` (n_cells entries) is
+ * overwritten.  Set-up call: synchronous, allocates a
  * temporary table, not capturable.  Errors: EINVAL (null pointers, reps
  * outside 1..1000), EHIP. */
 int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *images,

@@ -214,6 +214,13 @@ static int32_t plan_batch(const vsfe_params &p, int tile_w, int tile_h, int32_t 
         }
     }
     b->pyr_start[L] = (int32_t)b->h_pyr_items.size();
+    // single-launch schedule at the default tile (unavailable if a block
+    // would not fit: the per-level schedule is then the only one)
+    b->twr_ok = tower_plan(b, TWR_TW, TWR_TH);
+    if (b->twr_ok && (int)b->h_twr_items.size() < TWR_SMALL_ITEMS && !tower_plan(b, 64, 16))
+        b->twr_ok = tower_plan(b, TWR_TW, TWR_TH);
+    b->twr_def_w = b->twr_tw;
+    b->twr_def_h = b->twr_th;
     // detector tiles: whole cells, about tile_w x tile_h pixels at every level
     for (int l = 0; l < L; l++) {
         b->tile_w[l] = tile_w;
@@ -397,6 +404,7 @@ int32_t vsfe_batch_destroy(vsfe_batch *b) {
     if (b->d_run) (void)hipFree(b->d_run);
     if (b->d_item_list) (void)hipFree(b->d_item_list);
     if (b->d_row_tab) (void)hipFree(b->d_row_tab);
+    tower_release(b);
     cnn_release(b);
     delete b;
     return VSFE_OK;
@@ -424,6 +432,7 @@ int32_t vsfe_batch_create(const vsfe_ctx *ctx, int32_t n, const int32_t *widths,
     int32_t rc = plan_batch(ctx->p, ctx->tile_w, ctx->tile_h, n, widths, heights, pitches, offsets, b);
     if (!rc) rc = upload(b->images, &b->d_images);
     if (!rc) rc = upload(b->h_pyr_items, &b->d_pyr_items);
+    if (!rc && b->twr_ok) rc = tower_upload(b);
     if (!rc) rc = upload(b->h_coord, &b->d_coord);
     if (!rc) rc = upload(b->h_det_items, &b->d_det_items);
     if (!rc) rc = upload(b->h_chunks, &b->d_chunks);

@@ -81,6 +81,59 @@ static int32_t det_items_refresh(vsfe_batch *b) {
     return det_list_alloc(b);
 }
 
+// Pyramid schedule pass of the autotuner: the batch's current schedule
+// first (the baseline), then one launch per level and single-launch tiles
+// from small (more blocks, more halo) to large; tiles whose block does not
+// fit are skipped.  The fastest is installed.
+static int32_t tune_pyramid(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *images, uint8_t *pyr,
+                            int32_t *status, int reps, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                            vsfe_tune_report *out) {
+    struct Cand { int s, tw, th; };
+    int32_t s0, tw0, th0;
+    int32_t rc = vsfe_batch_pyramid_get(b, &s0, &tw0, &th0);
+    if (rc) return rc;
+    std::vector<Cand> cand{{s0, tw0, th0}};
+    if (s0 != VSFE_PYR_LEVELS) cand.push_back({VSFE_PYR_LEVELS, tw0, th0});
+    static const int kT[][2] = {{48, 8}, {64, 16}, {96, 24}, {112, 32}, {112, 48}, {160, 32}, {200, 24}, {240, 32}};
+    for (const auto &t : kT)
+        if (!(s0 == VSFE_PYR_TOWER && t[0] == tw0 && t[1] == th0)) cand.push_back({VSFE_PYR_TOWER, t[0], t[1]});
+    float best = 0.f;
+    int best_k = -1, tried = 0;
+    float worst = 0.f;
+    for (size_t k = 0; k < cand.size(); k++) {
+        rc = vsfe_batch_set_pyramid(b, cand[k].s, cand[k].tw, cand[k].th);
+        if (rc == VSFE_ECAPACITY) continue;   // this tile's block does not fit
+        if (rc) return rc;
+        rc = pyramid_build(ctx, b, images, pyr, status, st);   // warm-up
+        if (rc) return rc;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps && !rc; r++) rc = pyramid_build(ctx, b, images, pyr, status, st);
+        (void)hipEventRecord(e1, st);
+        if (rc) return rc;
+        if (hipEventSynchronize(e1) != hipSuccess) return fail(VSFE_EHIP, "tuning run failed");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const float us = ms * 1000.f / reps;
+        tried++;
+        if (k == 0) out->pyr_us_before = us;
+        worst = std::max(worst, us);
+        if (best_k < 0 || us < best) {
+            best = us;
+            best_k = (int)k;
+        }
+    }
+    if (best_k < 0) return fail(VSFE_EHIP, "no pyramid schedule could be timed");
+    rc = vsfe_batch_set_pyramid(b, cand[best_k].s, cand[best_k].tw, cand[best_k].th);
+    if (rc) return rc;
+    out->pyr_schedule = cand[best_k].s;
+    out->pyr_tile_w = cand[best_k].tw;
+    out->pyr_tile_h = cand[best_k].th;
+    out->pyr_us = best;
+    out->pyr_us_worst = worst;
+    out->pyr_n_tried = tried;
+    return VSFE_OK;
+}
+
 }  // namespace vsfe
 
 using namespace vsfe;
@@ -124,6 +177,15 @@ int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *i
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(VSFE_EHIP, "hipEventCreate failed");
+    if (L > 1) {
+        // the rebuilt pyramid is byte-identical whatever the schedule
+        rc = tune_pyramid(ctx, b, images, const_cast<uint8_t *>(pyr), status, reps, st, e0, e1, out);
+        if (rc) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc;
+        }
+    }
     DetItem *d_items = nullptr;
     size_t cap = 0;
     for (int l = 0; l < L && !rc; l++) {

@@ -50,6 +50,36 @@ struct PyrItem {
 };
 static_assert(sizeof(PyrItem) == 72, "PyrItem layout");
 
+// Single-launch pyramid ("tower"): a block owns one tile of every level of
+// one image (the tiles of level l partition it; those of level l+1 are the
+// outputs whose source falls in the block's tile of level l) and computes,
+// in LDS, the range of each level that its own tile and the next level's
+// computed range need.  Column and row plans are separate (the resampling
+// is separable); a block pairs one of each.
+constexpr int TWR_TW = 112;    // default owned tile at level 1, columns (multiple of 4)
+constexpr int TWR_TH = 32;     // ... rows
+constexpr int TWR_STAGE = 4;   // level-0 window: at most 4 x 256 16-byte chunks
+constexpr int TWR_TAB = 2048;  // table entries in LDS (both plans, all levels)
+constexpr int TWR_LDS = 60 * 1024;   // dynamic LDS limit (tables + two level buffers)
+constexpr int64_t TWR_AUTO_PIXELS = (int64_t)1 << 26;   // default schedule: single launch up to this many level-0 pixels
+constexpr int TWR_SMALL_ITEMS = 512;   // fewer blocks than this at the default tile: plan 64 x 16 instead
+// One plan of one axis (columns: quad-aligned ranges, level 0 16-aligned).
+struct TowerAxis {
+    int16_t c0[VSFE_MAX_LEVELS], cn[VSFE_MAX_LEVELS];  // computed range (level 0: staged window)
+    int16_t o0[VSFE_MAX_LEVELS], o1[VSFE_MAX_LEVELS];  // owned range [o0, o1), levels >= 1
+};
+static_assert(sizeof(TowerAxis) == 96, "TowerAxis layout");
+struct TowerItem {
+    int64_t src_offset;                 // level 0 of the image in the input buffer
+    int32_t sw, sh, spitch;             // its size and pitch
+    int32_t xs, ys, ncols, nrows;       // staged level-0 window (xs, ncols multiples of 16)
+    int32_t image, ax, ay;              // image record, column plan, row plan
+    int32_t tabx, ntabx, taby, ntaby;   // table entries of the two plans (levels 1.. in order)
+    int32_t odd_off;                    // LDS offset of the odd levels' buffer (even ones at 0)
+    int32_t pad;
+};
+static_assert(sizeof(TowerItem) == 72, "TowerItem layout");
+
 // Detector block: DET_WAVES waves of 64 lanes; a tile is at most 128 pixels
 // wide and 8 rows per wave high, at most 32 x DET_WAVES cells.
 #ifndef VSFE_DET_WAVES
@@ -108,6 +138,19 @@ struct vsfe_batch {
     std::vector<int32_t> pyr_start;
     std::vector<vsfe::PyrItem> h_pyr_items;
     vsfe::PyrItem *d_pyr_items = nullptr;
+    // single-launch pyramid: plans, tables (entry = window-local source
+    // index | weight << 16), items; twr_lds = dynamic LDS bytes of a block
+    int32_t pyr_schedule = 0;                    // VSFE_PYR_* as set (AUTO by default)
+    bool twr_ok = false;                         // plan fits (single launch available)
+    int32_t twr_tw = 0, twr_th = 0;              // owned level-1 tile of the plan
+    int32_t twr_def_w = 0, twr_def_h = 0;        // the batch's default tile (chosen at planning)
+    int32_t twr_tab_cap = 0, twr_lds = 0;
+    std::vector<vsfe::TowerAxis> h_twr_axes;
+    std::vector<uint32_t> h_twr_tab;
+    std::vector<vsfe::TowerItem> h_twr_items;
+    vsfe::TowerAxis *d_twr_axes = nullptr;
+    uint32_t *d_twr_tab = nullptr;
+    vsfe::TowerItem *d_twr_items = nullptr;
     // resampling tables: entry = source index | (weight << 16), weight 0 at the far edge
     std::vector<uint32_t> h_coord;
     uint32_t *d_coord = nullptr;
@@ -186,6 +229,14 @@ int32_t check_common(const vsfe_ctx *ctx, const vsfe_batch *b, int32_t *status);
 
 // proposer geometry of a batch (no-op below 4 levels) and its release;
 // cnn_plan_check: ECAPACITY when the proposer's 32-bit tables would overflow
+// single-launch pyramid plan of a batch (host, after the resampling tables)
+// for an owned level-1 tile of tw x th; false if a block would not fit
+bool tower_plan(vsfe_batch *b, int tw, int th);
+// schedule pyramid_build uses (VSFE_PYR_LEVELS or VSFE_PYR_TOWER)
+int32_t pyr_schedule_resolved(const vsfe_batch *b);
+// upload the plan (freeing any previous one)
+int32_t tower_upload(vsfe_batch *b);
+void tower_release(vsfe_batch *b);
 int32_t cnn_plan_check(const vsfe_batch *b);
 int32_t cnn_setup(vsfe_batch *b);
 void cnn_release(vsfe_batch *b);

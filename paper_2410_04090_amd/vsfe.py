@@ -66,14 +66,20 @@ class TuneReport(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("tile_w", C.c_int32 * MAX_LEVELS), ("tile_h", C.c_int32 * MAX_LEVELS),
                 ("us", C.c_float * MAX_LEVELS), ("us_before", C.c_float * MAX_LEVELS),
                 ("n_tried", C.c_int32 * MAX_LEVELS), ("us_worst", C.c_float * MAX_LEVELS),
-                ("us_median", C.c_float * MAX_LEVELS)]
+                ("us_median", C.c_float * MAX_LEVELS), ("pyr_schedule", C.c_int32), ("pyr_tile_w", C.c_int32),
+                ("pyr_tile_h", C.c_int32), ("pyr_us", C.c_float), ("pyr_us_before", C.c_float),
+                ("pyr_us_worst", C.c_float), ("pyr_n_tried", C.c_int32)]
 
     def as_dict(self):
         n = self.n_levels
         return {"tile_w": list(self.tile_w[:n]), "tile_h": list(self.tile_h[:n]),
                 "us": [round(x, 2) for x in self.us[:n]], "us_before": [round(x, 2) for x in self.us_before[:n]],
                 "n_tried": list(self.n_tried[:n]), "us_worst": [round(x, 2) for x in self.us_worst[:n]],
-                "us_median": [round(x, 2) for x in self.us_median[:n]]}
+                "us_median": [round(x, 2) for x in self.us_median[:n]],
+                "pyramid": {"schedule": {PYR_LEVELS: "levels", PYR_TOWER: "tower"}.get(self.pyr_schedule, "none"),
+                            "tile": [self.pyr_tile_w, self.pyr_tile_h], "us": round(self.pyr_us, 2),
+                            "us_before": round(self.pyr_us_before, 2), "us_worst": round(self.pyr_us_worst, 2),
+                            "n_tried": self.pyr_n_tried}}
 
 
 EXPORTS = ["vsfe_params_default", "vsfe_params_check", "vsfe_level_geometry", "vsfe_ctx_create",
@@ -83,7 +89,8 @@ EXPORTS = ["vsfe_params_default", "vsfe_params_check", "vsfe_level_geometry", "v
            "stereo_match", "vsfe_cnn_info_get", "cnn_forward", "cnn_propose", "cnn_backward", "cnn_adam_step",
            "vsfe_batch_tiles_get", "vsfe_batch_set_tiles", "vsfe_batch_autotune", "pyca_cull_aggregate_noalloc",
            "stereo_refine", "vsfe_feature_match_workspace", "feature_match",
-           "vsfe_fc_cull_stride", "fc_cull_crf", "pyramid_build_levels"]
+           "vsfe_fc_cull_stride", "fc_cull_crf", "pyramid_build_levels", "vsfe_batch_set_pyramid",
+           "vsfe_batch_pyramid_get"]
 
 NOALLOC_MAX_CELLS = 1 << 22
 
@@ -126,6 +133,10 @@ def lib():
     L.vsfe_batch_tiles_get.restype = i32
     L.vsfe_batch_set_tiles.argtypes = [vp, pi32, pi32]
     L.vsfe_batch_set_tiles.restype = i32
+    L.vsfe_batch_set_pyramid.argtypes = [vp, i32, i32, i32]
+    L.vsfe_batch_set_pyramid.restype = i32
+    L.vsfe_batch_pyramid_get.argtypes = [vp, pi32, pi32, pi32]
+    L.vsfe_batch_pyramid_get.restype = i32
     L.vsfe_batch_autotune.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, C.POINTER(TuneReport)]
     L.vsfe_batch_autotune.restype = i32
     L.vsfe_last_error.argtypes = []
@@ -263,6 +274,20 @@ def batch_set_tiles(b, tile_w, tile_h):
     w = (C.c_int32 * MAX_LEVELS)(*tile_w)
     h = (C.c_int32 * MAX_LEVELS)(*tile_h)
     _check(lib().vsfe_batch_set_tiles(b, w, h))
+
+
+PYR_AUTO, PYR_LEVELS, PYR_TOWER = 0, 1, 2
+
+
+def batch_set_pyramid(b, schedule, tile_w=0, tile_h=0):
+    _check(lib().vsfe_batch_set_pyramid(b, schedule, tile_w, tile_h))
+
+
+def batch_pyramid_get(b):
+    """(schedule pyramid_build uses, single-launch tile width, height)."""
+    s, w, h = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().vsfe_batch_pyramid_get(b, C.byref(s), C.byref(w), C.byref(h)))
+    return s.value, w.value, h.value
 
 
 def batch_autotune(ctx, b, images, pyr, cell_keys, status, reps=5, stream=None) -> TuneReport:

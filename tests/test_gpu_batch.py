@@ -62,6 +62,14 @@ def test_autotune_keeps_results(fe_mod, pattern):
             assert c <= rep["tile_w"][l] <= max(128, c) and c <= rep["tile_h"][l] <= max(32, c)
             assert rep["n_tried"][l] >= 1 and rep["us"][l] > 0 and rep["us"][l] <= rep["us_before"][l]
             assert tw[l] // c == rep["tile_w"][l] // c and th[l] // c == rep["tile_h"][l] // c
+        # the pyramid pass timed both schedules and installed the one it reports
+        from paper_2410_04090_amd import vsfe
+        pr = rep["pyramid"]
+        assert pr["n_tried"] >= 3 and pr["us"] > 0 and pr["us_worst"] >= pr["us"]
+        sched, ptw, pth = vsfe.batch_pyramid_get(fe.batch)
+        assert pr["schedule"] == {vsfe.PYR_LEVELS: "levels", vsfe.PYR_TOWER: "tower"}[sched]
+        if sched == vsfe.PYR_TOWER:
+            assert [ptw, pth] == pr["tile"]
         fe.run()
         torch.cuda.synchronize()
         assert_same(before, snapshot(fe))

@@ -275,3 +275,74 @@ def test_level_ranges_match_full_detection(fe_mod, pattern):
                 vsfe.fast_br_detect_levels(c, b, fe.images, fe.pyr, None, fe.cell_keys, lo, hi, fe.status)
     finally:
         fe.close()
+
+
+@pytest.mark.parametrize("sizes,levels", [
+    ([(1241, 376), (1241, 376)], 8),
+    ([(97, 61), (640, 17), (33, 33), (1920, 1080), (257, 193), (17, 9)], 8),
+    ([(8192, 160), (160, 8192)], 8),
+    ([(130, 77), (97, 61), (17, 9)], 12),
+])
+def test_pyramid_schedules(fe_mod, pattern, sizes, levels):
+    """Both pyramid schedules (one launch per level; one launch for all
+    levels with per-block halos) and several single-launch tiles write
+    every level of every image exactly as the oracle builds it; pixels the
+    schedule must not touch (row padding) keep their poison value."""
+    import torch
+    from paper_2410_04090_amd import vsfe
+    p = Params(n_levels=levels)
+    imgs = [scenes.random_image(900 + k, w, h) for k, (w, h) in enumerate(sizes)]
+    fe = fe_mod.Frontend(p, sizes, pattern)
+    try:
+        fe.upload(imgs)
+        cases = [(vsfe.PYR_LEVELS, 0, 0), (vsfe.PYR_TOWER, 0, 0), (vsfe.PYR_TOWER, 16, 4),
+                 (vsfe.PYR_TOWER, 48, 8), (vsfe.PYR_TOWER, 128, 32), (vsfe.PYR_TOWER, 240, 4)]
+        for sched, tw, th in cases:
+            say("case: sizes=%s L=%d schedule=%d tile=%dx%d" % (sizes, levels, sched, tw, th))
+            try:
+                vsfe.batch_set_pyramid(fe.batch, sched, tw, th)
+            except vsfe.VsfeError as e:
+                # only a single-launch tile whose block does not fit may be refused
+                assert sched == vsfe.PYR_TOWER and e.code == vsfe.ECAPACITY, e
+                continue
+            got = vsfe.batch_pyramid_get(fe.batch)
+            assert got[0] == sched
+            fe.pyr.fill_(0xA5)
+            vsfe.pyramid_build(fe.ctx, fe.batch, fe.images, fe.pyr, fe.status)
+            torch.cuda.synchronize()
+            assert int(fe.status.item()) == 0
+            for i, img in enumerate(imgs):
+                compare_pyramid(fe, i, img, p)
+                for l in range(1, levels):
+                    li = fe.level_info(i, l)
+                    if li.pitch > li.width:
+                        pad = fe.pyr[li.offset:li.offset + li.pitch * li.height].cpu().numpy()
+                        pad = pad.reshape(li.height, li.pitch)[:, li.width:]
+                        assert (pad == 0xA5).all(), (i, l)
+        vsfe.batch_set_pyramid(fe.batch, vsfe.PYR_AUTO)
+    finally:
+        fe.close()
+
+
+def test_pyramid_schedule_errors(fe_mod, pattern):
+    """Unknown schedules and tiles out of range are refused; a refused tile
+    leaves the batch working."""
+    from paper_2410_04090_amd import vsfe
+    fe = fe_mod.Frontend(Params(), [(400, 256)], pattern)
+    try:
+        before = vsfe.batch_pyramid_get(fe.batch)
+        # a single small image: the single-launch schedule with the small-batch tile
+        assert before == (vsfe.PYR_TOWER, 64, 16)
+        for sched, tw, th in ((3, 0, 0), (-1, 0, 0), (vsfe.PYR_TOWER, 18, 8), (vsfe.PYR_TOWER, 12, 8),
+                              (vsfe.PYR_TOWER, 244, 8), (vsfe.PYR_TOWER, 64, 3), (vsfe.PYR_TOWER, 64, 65)):
+            with pytest.raises(vsfe.VsfeError) as ei:
+                vsfe.batch_set_pyramid(fe.batch, sched, tw, th)
+            assert ei.value.code == vsfe.EINVAL
+        assert vsfe.batch_pyramid_get(fe.batch) == before
+        # explicit default tile (0 x 0) and back to the automatic choice
+        vsfe.batch_set_pyramid(fe.batch, vsfe.PYR_LEVELS)
+        assert vsfe.batch_pyramid_get(fe.batch) == (vsfe.PYR_LEVELS, 64, 16)
+        vsfe.batch_set_pyramid(fe.batch, vsfe.PYR_AUTO)
+        assert vsfe.batch_pyramid_get(fe.batch) == before
+    finally:
+        fe.close()
