@@ -127,6 +127,32 @@ def stored_counters(call, workload):
         return None
 
 
+def stored_ceiling():
+    """VALU issue rate measured by the probe kernel (wave instructions/s)
+    from profiles/ceiling_probe_mi355x.txt, or None when absent or the probe
+    source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "ceiling_probe_mi355x.txt")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in ("probe.hip", "vsfe_internal.h"):
+        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.split("(")[0].strip()
+    if kv.get("source_sha") != h.hexdigest()[:16]:
+        return None
+    try:
+        return float(kv["valu_wave_insts_per_s"])
+    except (KeyError, ValueError):
+        return None
+
+
 # VALU issue peak: one wave64 instruction per SIMD every 4 cycles (16 lanes
 # per SIMD), 4 SIMDs per CU, 256 CUs at 2.4 GHz: 256 x 4 x 2.4e9 / 4 =
 # 614 G wave-instructions/s = 39.3 T lane-operations/s
@@ -145,6 +171,45 @@ def copy_probe(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 5}), flush=True)
+
+
+def ceiling_probe():
+    """Measured VALU issue rate and LDS read bandwidth of the device (the
+    library's probe kernels), against the figures the roofline assumes."""
+    import torch
+    from paper_2410_04090_amd import vsfe
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"cus": n_cu}
+    for kind, name, iters in ((vsfe.PROBE_VALU, "valu", 2000), (vsfe.PROBE_LDS, "lds", 4000)):
+        blocks = n_cu * 8
+        sink = torch.zeros(blocks * 256, dtype=torch.int32, device="cuda")
+        clocks = torch.zeros(2, dtype=torch.int64, device="cuda")
+        st = torch.cuda.current_stream()
+        vsfe.probe(kind, blocks, iters // 10, sink, clocks, st)   # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record(st)
+        for _ in range(reps):
+            vsfe.probe(kind, blocks, iters, sink, clocks, st)
+        e1.record(st)
+        e1.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        cyc, wall = clocks.cpu().tolist()
+        ghz = cyc / (wall / 100e6) / 1e9 if wall else None
+        waves = blocks * 4
+        if kind == vsfe.PROBE_VALU:
+            insts = waves * 128 * iters
+            rate = insts / sec
+            out[name] = {"wave_insts": insts, "us": round(sec * 1e6, 1), "wave_insts_per_s": round(rate / 1e9, 1),
+                         "unit": "G/s", "assumed_peak": round(VALU_WAVE_INSTS_PER_S / 1e9, 1),
+                         "frac_of_assumed": round(rate / VALU_WAVE_INSTS_PER_S, 3), "sclk_ghz": round(ghz, 3) if ghz else None}
+        else:
+            nbytes = waves * 64 * 16 * 16 * iters
+            bw = nbytes / sec
+            out[name] = {"bytes": nbytes, "us": round(sec * 1e6, 1), "bytes_per_s": round(bw / 1e12, 2), "unit": "TB/s",
+                         "bytes_per_clk_per_cu": round(bw / (n_cu * (ghz or 2.4) * 1e9), 1),
+                         "sclk_ghz": round(ghz, 3) if ghz else None}
+    print(json.dumps({"ceiling_probe": out}), flush=True)
 
 
 def load_proposer(path):
@@ -348,7 +413,12 @@ def main():
     ap.add_argument("--proposer", default=None, help="proposer weights (default: the packaged ones for the image size)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--probe", action="store_true",
+                    help="only measure the VALU issue rate and LDS bandwidth ceilings and exit")
     args = ap.parse_args()
+    if args.probe:
+        ceiling_probe()
+        return
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
@@ -463,6 +533,11 @@ def main():
                 "peak": round(VALU_LANE_OPS_PEAK_T, 1), "unit": "T lane-ops/s (issued int32 VALU)",
                 "frac": round(issue, 4), "insts_valu_per_launch": sq["insts_valu_per_launch"],
                 "insts_salu_per_launch": sq["insts_salu_per_launch"]}
+        ceil = stored_ceiling()
+        if ceil is not None:
+            # the same issue rate against what the probe kernel reaches on this chip
+            valu["measured_ceiling_wave_insts_per_s"] = ceil
+            valu["frac_of_measured_ceiling"] = round(sq["insts_valu_per_launch"] / (call_us[dominant] * 1e-6) / ceil, 4)
     if valu is not None and valu["frac"] > hbm["frac"]:
         roof = {"kernel": dominant, "bound": "alu", "achieved": valu["achieved"], "peak": valu["peak"],
                 "unit": valu["unit"], "frac": valu["frac"], "traffic": traffic, "hbm": hbm, "valu": valu}

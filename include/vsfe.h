@@ -249,6 +249,23 @@ int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *i
                             const uint8_t *pyr, uint32_t *cell_keys, int32_t *status,
                             int32_t reps, void *stream, vsfe_tune_report *out);
 
+/* ---------------------------------------------- measurement aids (not the
+ * paper's method): device ceilings the kernels are compared against. */
+
+/* kind VSFE_PROBE_VALU: `blocks` x 256 threads, each running 8 independent
+ * float FMA chains for 128 x iters VALU instructions per wave (plus a few);
+ * kind VSFE_PROBE_LDS: each thread reads 16 x iters conflict-free 16-byte
+ * LDS words (ds_read_b128, 1 KB per wave instruction).  sink: device
+ * buffer of blocks x 256 x 4 bytes (written only in a case that does not
+ * occur, so that the work is kept); clocks (device, 2 x uint64, written):
+ * shader-clock cycles and 100 MHz wall-clock ticks that block 0 spent in
+ * its loop, whose ratio is the clock the device ran at.  Time the call with
+ * events on `stream`.  Errors: EINVAL (kind, blocks or iters outside
+ * 1..2^20, null buffers), EHIP. */
+#define VSFE_PROBE_VALU 1
+#define VSFE_PROBE_LDS  2
+int32_t vsfe_probe(int32_t kind, int32_t blocks, int32_t iters, void *sink, uint64_t *clocks, void *stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char *vsfe_last_error(void);
 

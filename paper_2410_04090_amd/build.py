@@ -14,7 +14,7 @@ LIB = os.path.join(PKG, "libvsfe.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
 SOURCES = ["api.hip", "pyramid.hip", "detect.hip", "pyca.hip", "orb.hip", "stereo.hip", "refine.hip", "track.hip",
-           "fc.hip", "cnn.hip", "tune.hip"]
+           "fc.hip", "cnn.hip", "tune.hip", "probe.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -14,9 +14,10 @@
 // source rows are uniform per wave: every needed source row is lerped
 // horizontally once, two columns per packed 16-bit multiply-add
 // (a (256 - fx) + b fx <= 65280 fits), with the 4 source bytes of a column
-// pair gathered by one v_perm from two LDS dwords; the vertical lerp is a
-// 32-bit multiply-add per output whose byte 2 is the rounded result, and the
-// 4 outputs are stored as one 32-bit word.
+// pair gathered by one v_perm from two LDS dwords; the vertical lerp is one
+// v_dot2_u32_u16 per output (its top / bottom pair gathered by one v_perm)
+// whose byte 2 is the rounded result, and the 4 outputs are stored as one
+// 32-bit word.
 #include "vsfe_internal.h"
 
 namespace vsfe {
@@ -25,6 +26,23 @@ constexpr int PYR_LDS_W = PYR_SW + 16;  // padded row stride (bank spread), 16-b
 constexpr int PYR_TASKS = (PYR_SH * (PYR_SW / 16) + 255) / 256;
 
 typedef unsigned short pu2 __attribute__((ext_vector_type(2)));
+
+// Vertical lerp of four columns: byte 2 of h_top (256 - fy) + h_bot fy +
+// 2^15 (< 2^24) per column, from the horizontal lerps of the top and bottom
+// source rows as u16 pairs (t01, t23 / u01, u23).  Each column's (top,
+// bottom) pair is gathered into one register by v_perm and weighted by one
+// v_dot2_u32_u16 against wf = (256 - fy, fy); the four bytes 2 pack into a
+// word.
+__device__ __forceinline__ uint32_t vlerp4(pu2 t01, pu2 t23, pu2 u01, pu2 u23, uint32_t wf) {
+    const pu2 W = __builtin_bit_cast(pu2, wf);
+    const uint32_t a01 = __builtin_bit_cast(uint32_t, t01), b01 = __builtin_bit_cast(uint32_t, u01);
+    const uint32_t a23 = __builtin_bit_cast(uint32_t, t23), b23 = __builtin_bit_cast(uint32_t, u23);
+    const uint32_t s0 = __builtin_amdgcn_udot2(__builtin_bit_cast(pu2, __builtin_amdgcn_perm(b01, a01, 0x05040100u)), W, 32768u, false);
+    const uint32_t s1 = __builtin_amdgcn_udot2(__builtin_bit_cast(pu2, __builtin_amdgcn_perm(b01, a01, 0x07060302u)), W, 32768u, false);
+    const uint32_t s2 = __builtin_amdgcn_udot2(__builtin_bit_cast(pu2, __builtin_amdgcn_perm(b23, a23, 0x05040100u)), W, 32768u, false);
+    const uint32_t s3 = __builtin_amdgcn_udot2(__builtin_bit_cast(pu2, __builtin_amdgcn_perm(b23, a23, 0x07060302u)), W, 32768u, false);
+    return __builtin_amdgcn_perm(s1, s0, 0x0C0C0602u) | (__builtin_amdgcn_perm(s3, s2, 0x0C0C0602u) << 16);
+}
 
 // 16 consecutive bytes of a row from x, coordinates clamped to [0, w).
 __device__ __forceinline__ uint4 fetch16c(const uint8_t *row, int x, int w, bool aligned) {
@@ -124,7 +142,7 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
         if (oy >= d.h) break;                            // uniform
         const uint32_t e = ey[k];
         const int ya = (int)(e & 0xFFFFu) - it.ys;
-        const uint32_t fy = e >> 16, wy = 256u - fy;
+        const uint32_t fy = e >> 16, wf = (256u - fy) | (fy << 16);
         if (ya == cur + 1) {                             // slide by one row
             t01 = u01;
             t23 = u23;
@@ -135,11 +153,7 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
         }
         cur = ya;
         // (h0 (256 - fy) + h1 fy + 2^15) >> 16 is byte 2 of the sum
-        const uint32_t s0 = (uint32_t)t01.x * wy + (uint32_t)u01.x * fy + 32768u;
-        const uint32_t s1 = (uint32_t)t01.y * wy + (uint32_t)u01.y * fy + 32768u;
-        const uint32_t s2 = (uint32_t)t23.x * wy + (uint32_t)u23.x * fy + 32768u;
-        const uint32_t s3 = (uint32_t)t23.y * wy + (uint32_t)u23.y * fy + 32768u;
-        const uint32_t word = __builtin_amdgcn_perm(s1, s0, 0x0C0C0602u) | (__builtin_amdgcn_perm(s3, s2, 0x0C0C0602u) << 16);
+        const uint32_t word = vlerp4(t01, t23, u01, u23, wf);
         if (ox + 3 < d.w) {
             *(uint32_t *)out = word;
         } else {
@@ -280,7 +294,7 @@ __global__ __launch_bounds__(256) void pyramid_tower_kernel(const ImageDev *__re
             for (int r = r0; r < r1; r++) {
                 const uint32_t e = s_tab[yoff + r];
                 const int ya = (int)(e & 0xFFFFu);
-                const uint32_t fy = e >> 16, wy = 256u - fy;
+                const uint32_t fy = e >> 16, wf = (256u - fy) | (fy << 16);
                 if (ya == cur + 1) {
                     t01 = u01;
                     t23 = u23;
@@ -290,12 +304,7 @@ __global__ __launch_bounds__(256) void pyramid_tower_kernel(const ImageDev *__re
                     hrow(ya + 1, u01, u23);
                 }
                 cur = ya;
-                const uint32_t s0 = (uint32_t)t01.x * wy + (uint32_t)u01.x * fy + 32768u;
-                const uint32_t s1 = (uint32_t)t01.y * wy + (uint32_t)u01.y * fy + 32768u;
-                const uint32_t s2 = (uint32_t)t23.x * wy + (uint32_t)u23.x * fy + 32768u;
-                const uint32_t s3 = (uint32_t)t23.y * wy + (uint32_t)u23.y * fy + 32768u;
-                const uint32_t word =
-                    __builtin_amdgcn_perm(s1, s0, 0x0C0C0602u) | (__builtin_amdgcn_perm(s3, s2, 0x0C0C0602u) << 16);
+                const uint32_t word = vlerp4(t01, t23, u01, u23, wf);
                 *(uint32_t *)(db + r * dst_stride + 4 * q) = word;
                 const int gy = cy0 + r;
                 if (own_x && gy >= oy0 && gy < oy1) {

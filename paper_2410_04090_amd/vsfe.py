@@ -90,7 +90,7 @@ EXPORTS = ["vsfe_params_default", "vsfe_params_check", "vsfe_level_geometry", "v
            "vsfe_batch_tiles_get", "vsfe_batch_set_tiles", "vsfe_batch_autotune", "pyca_cull_aggregate_noalloc",
            "stereo_refine", "vsfe_feature_match_workspace", "feature_match",
            "vsfe_fc_cull_stride", "fc_cull_crf", "pyramid_build_levels", "vsfe_batch_set_pyramid",
-           "vsfe_batch_pyramid_get"]
+           "vsfe_batch_pyramid_get", "vsfe_probe"]
 
 NOALLOC_MAX_CELLS = 1 << 22
 
@@ -133,6 +133,8 @@ def lib():
     L.vsfe_batch_tiles_get.restype = i32
     L.vsfe_batch_set_tiles.argtypes = [vp, pi32, pi32]
     L.vsfe_batch_set_tiles.restype = i32
+    L.vsfe_probe.argtypes = [i32, i32, i32, vp, vp, vp]
+    L.vsfe_probe.restype = i32
     L.vsfe_batch_set_pyramid.argtypes = [vp, i32, i32, i32]
     L.vsfe_batch_set_pyramid.restype = i32
     L.vsfe_batch_pyramid_get.argtypes = [vp, pi32, pi32, pi32]
@@ -277,6 +279,13 @@ def batch_set_tiles(b, tile_w, tile_h):
 
 
 PYR_AUTO, PYR_LEVELS, PYR_TOWER = 0, 1, 2
+PROBE_VALU, PROBE_LDS = 1, 2
+
+
+def probe(kind, blocks, iters, sink, clocks, stream=None):
+    """Launch a ceiling probe (sink: blocks x 256 int32/float device tensor,
+    clocks: 2 int64 device tensor)."""
+    _check(lib().vsfe_probe(kind, blocks, iters, _p(sink), _p(clocks), _stream(stream)))
 
 
 def batch_set_pyramid(b, schedule, tile_w=0, tile_h=0):

@@ -118,3 +118,17 @@ def test_batch_plan_refuses_proposer_overflow():
     # the same images with 3 levels (no proposer) plan fine
     info = vsfe.batch_plan(vsfe.make_params(n_levels=3), [side] * 2, [side] * 2, [side] * 2, [0, side * side])
     assert info.n_images == 2
+
+
+def test_probe_argument_checks():
+    """The ceiling probes reject unknown kinds, sizes out of range and null
+    buffers on the host, before any launch."""
+    L = vsfe.lib()
+    dummy = C.c_void_p(16)
+    for kind, blocks, iters, sink, clocks in ((0, 1, 1, dummy, dummy), (3, 1, 1, dummy, dummy),
+                                              (vsfe.PROBE_VALU, 0, 1, dummy, dummy),
+                                              (vsfe.PROBE_LDS, 1, 0, dummy, dummy),
+                                              (vsfe.PROBE_VALU, 1 << 21, 1, dummy, dummy),
+                                              (vsfe.PROBE_VALU, 1, 1, None, dummy),
+                                              (vsfe.PROBE_LDS, 1, 1, dummy, None)):
+        assert L.vsfe_probe(kind, blocks, iters, sink, clocks, None) == vsfe.EINVAL
