@@ -115,12 +115,48 @@ def test_trained_proposer_gain(torch_mod):
         say("trained (packaged threshold): recall %.4f, cells kept %.3f" % (rec_t, kept_t))
         say("untrained, best threshold at 99%% recall: recall %.4f, cells kept %.3f" % (rec_u, kept_u))
         say("intensity range, best threshold at 99%% recall: recall %.4f, cells kept %.3f" % (rec_c, kept_c))
-        # the calibrated threshold carries over to unseen pairs
-        assert rec_t >= 0.98
+        # the calibrated threshold carries over to unseen pairs (measured 0.9929)
+        assert rec_t >= 0.99
         # gain over the method without a proposer: a sizeable share of cells is skipped
         assert kept_t <= 0.85
         # and it comes from training: the untrained network, even with its
         # threshold picked on these pairs, keeps clearly more cells
         assert kept_t <= kept_u - 0.05
+    finally:
+        fe.close()
+
+
+@pytest.mark.skip(reason="not met: on these held-out pairs the trained network keeps 70.2 % of the cells at "
+                         "99.29 % recall, the non-learned level-3 intensity range 66.7 % at 99.16 % (its threshold "
+                         "picked on the same pairs); the network does not beat that statistic on this workload")
+def test_trained_proposer_beats_intensity_range(torch_mod):
+    """The trained network should keep fewer cells than the intensity-range
+    proposer at 99 % recall (kept_t < kept_c)."""
+    torch = torch_mod
+    from paper_2410_04090_amd import labels
+    from paper_2410_04090_amd.frontend import Frontend
+    d = np.load(WEIGHTS, allow_pickle=False)
+    import json
+    meta = json.loads(str(d["meta"]))
+    tau_trained = float(meta["thresholds"]["%dx%d" % (W, H)])
+    theta_trained = d["params"].astype(np.float32)
+    imgs = [im for s in SEEDS for im in scenes.stereo_pair(s, W, H, 800, 128)]
+    p = Params(n_max=4000, d_max=128)
+    fe = Frontend(p, [(W, H)] * len(imgs), pat.brief_pattern())
+    try:
+        fe.upload(imgs)
+        fe.run(describe=False)
+        exact, native = keypoint_sets(torch, fe)
+        pos = np.concatenate([labels.positive_cells(x0, y0, W, H).reshape(-1) for x0, y0 in native]).astype(bool)
+        from paper_2410_04090_amd import vsfe
+        wb = torch.from_numpy(theta_trained).cuda().to(torch.bfloat16).view(torch.int16).contiguous()
+        vsfe.cnn_propose(fe.ctx, fe.batch, fe.pyr, wb, 0.0, fe.cnn_ws, fe.grid_logits, fe.cell_logits,
+                         fe.cell_mask, fe.status)
+        torch.cuda.synchronize()
+        rec_t, kept_t = gated_recall(torch, fe, exact, fe.cell_logits.cpu().numpy() >= tau_trained)
+        con = np.concatenate([labels.contrast_scores(fe.pyramid_levels(i)[3], W, H).reshape(-1)
+                              for i in range(fe.n)])
+        _, rec_c, kept_c = best_at_recall(torch, fe, exact, con, pos)
+        assert rec_t >= 0.99 and kept_t < kept_c
     finally:
         fe.close()
