@@ -367,7 +367,11 @@ def culling_ablation(args, wl, fe, stream):
     from paper_2410_04090_amd import vsfe
     c, b = fe.ctx, fe.batch
     crf = torch.zeros(max(int(fe.info.crf_elems), 1), dtype=torch.int16, device="cuda")
-    keys = torch.zeros(max(int(fe.info.n_cells), 1) * 16, dtype=torch.int32, device="cuda")
+    # the keys of the largest (level, cell) queried: n_images x its stride
+    cells = [(lv, int(fe.level_info(0, lv).cell)) for lv in range(wl.params.n_levels)]
+    cells += [(0, cell) for cell in (23, 17, 13, 7, 3)]
+    n_keys = max(fe.n * vsfe.fc_cull_stride(b, lv, cell) for lv, cell in cells)
+    keys = torch.zeros(max(n_keys, 1), dtype=torch.int32, device="cuda")
     fused = time_call(lambda: vsfe.fast_br_detect(c, b, fe.images, fe.pyr, None, fe.cell_keys, None, fe.status,
                                                   stream), args.kernel_reps, stream)
     dump = time_call(lambda: vsfe.fast_br_detect(c, b, fe.images, fe.pyr, None, fe.cell_keys, crf, fe.status,

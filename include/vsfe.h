@@ -421,12 +421,15 @@ int32_t feature_match(const vsfe_ctx *ctx, const vsfe_batch *b, const vsfe_kp_so
  * floor(128 / cell) cells); scheme 1: log2 tree reduction, one block and
  * one thread per pixel of a cell; scheme 2: scheme 0 with one block per
  * cell.  keys: image i's cells row-major from i * stride
- * (vsfe_fc_cull_stride).  EINVAL: level out of range, cell outside 1..32,
- * scheme outside 0..2, n_loc outside 1..32 or ceil(cell / n_loc) > 8
- * (schemes 0 and 2). */
+ * (vsfe_fc_cull_stride), keys_elems = its size in entries, at least
+ * n_images x stride for this level and cell (ECAPACITY otherwise, before
+ * any launch).  EINVAL: level out of range, cell outside 1..32, scheme
+ * outside 0..2, n_loc outside 1..32 or ceil(cell / n_loc) > 8 (schemes 0
+ * and 2). */
 int32_t vsfe_fc_cull_stride(const vsfe_batch *b, int32_t level, int32_t cell, int64_t *stride);
 int32_t fc_cull_crf(const vsfe_ctx *ctx, const vsfe_batch *b, const uint16_t *crf, int32_t level, int32_t cell,
-                    int32_t scheme, int32_t n_loc, uint32_t *keys, int32_t *status, void *stream);
+                    int32_t scheme, int32_t n_loc, uint32_t *keys, int64_t keys_elems, int32_t *status,
+                    void *stream);
 
 /* ---------------------------------------------------- learned cell proposer
  *

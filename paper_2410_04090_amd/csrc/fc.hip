@@ -132,8 +132,8 @@ extern "C" int32_t vsfe_fc_cull_stride(const vsfe_batch *b, int32_t level, int32
 }
 
 extern "C" int32_t fc_cull_crf(const vsfe_ctx *ctx, const vsfe_batch *b, const uint16_t *crf, int32_t level,
-                               int32_t cell, int32_t scheme, int32_t n_loc, uint32_t *keys, int32_t *status,
-                               void *stream) {
+                               int32_t cell, int32_t scheme, int32_t n_loc, uint32_t *keys, int64_t keys_elems,
+                               int32_t *status, void *stream) {
     int32_t rc = check_common(ctx, b, status);
     if (rc) return rc;
     if (!crf || !keys) return fail(VSFE_EINVAL, "null buffer");
@@ -147,6 +147,13 @@ extern "C" int32_t fc_cull_crf(const vsfe_ctx *ctx, const vsfe_batch *b, const u
     int mx, my;
     a.stride = fc_stride(b, level, cell, &mx, &my);
     if (b->n_images > 65535 || my > 65535) return fail(VSFE_ECAPACITY, "grid too large");
+    // the output depends on (level, cell): its size is checked here, before
+    // any launch, rather than trusted
+    const int64_t need = (int64_t)b->n_images * a.stride;
+    if (keys_elems < need)
+        return fail(VSFE_ECAPACITY, "keys holds " + std::to_string((long long)keys_elems) + " entries; level " +
+                                        std::to_string(level) + " with cell " + std::to_string(cell) + " needs " +
+                                        std::to_string((long long)need) + " (n_images x vsfe_fc_cull_stride)");
     hipStream_t st = (hipStream_t)stream;
     if (scheme == 1) {
         a.n_loc = a.nt = a.cpb = 1;

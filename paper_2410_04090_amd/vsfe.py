@@ -156,7 +156,7 @@ def lib():
     L.feature_match.argtypes = [vp, vp, C.POINTER(KpSoa), vp, vp, C.POINTER(KpSoa), vp, vp, i32, i32, i32, i32, vp,
                                 vp, vp, vp, vp, vp]
     L.vsfe_fc_cull_stride.argtypes = [vp, i32, i32, pi64]
-    L.fc_cull_crf.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp, vp]
+    L.fc_cull_crf.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, i64, vp, vp]
     L.vsfe_cnn_info_get.argtypes = [vp, C.POINTER(CnnInfo)]
     L.cnn_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.cnn_propose.argtypes = [vp, vp, vp, vp, C.c_float, vp, vp, vp, vp, vp, vp]
@@ -385,8 +385,11 @@ def fc_cull_stride(b, level, cell) -> int:
 
 
 def fc_cull_crf(ctx, b, crf, level, cell, scheme, n_loc, keys, status, stream=None):
-    _check(lib().fc_cull_crf(ctx, b, _p(crf), int(level), int(cell), int(scheme), int(n_loc), _p(keys), _p(status),
-                             _stream(stream)))
+    """keys: a 4-byte device tensor; its size is passed on and checked by
+    the library (n_images x fc_cull_stride(b, level, cell) entries)."""
+    assert keys.element_size() == 4, "keys holds uint32 entries"
+    _check(lib().fc_cull_crf(ctx, b, _p(crf), int(level), int(cell), int(scheme), int(n_loc), _p(keys),
+                             int(keys.numel()), _p(status), _stream(stream)))
 
 
 # ------------------------------------------------------------- learned proposer
