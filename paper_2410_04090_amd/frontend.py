@@ -135,9 +135,11 @@ class Frontend:
         stereo = self.stereo if stereo is None else stereo
         c, b = self.ctx, self.batch
         L = self.params.n_levels
-        if L > 4:
+        if L > 4 and vsfe.batch_pyramid_get(b)[0] == vsfe.PYR_LEVELS:
             # levels 1..3 feed the proposer; levels 4.. are built on a second
             # stream while it runs, and the branches join before detection
+            # (with the single-launch schedule the whole pyramid comes first:
+            # one launch is shorter than the split's seven)
             st = stream if stream is not None else torch.cuda.current_stream()
             vsfe.pyramid_build_levels(c, b, self.images, self.pyr, 1, 4, self.status, st)
             side = self._side()
