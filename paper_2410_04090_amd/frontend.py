@@ -96,12 +96,18 @@ class Frontend:
     # synchronisation costs more than the overlap saves (one 1241 x 376 pair
     # loses about 20 us, 32 mixed pairs gain)
     OVERLAP_MIN_PIXELS = 4_000_000
+    # with one pyramid launch per level, levels 1..OVERLAP_SPLIT are also
+    # detected on the second stream (splits after levels 2..5 measured
+    # within 4 µs of each other on 64 1080p pairs)
+    OVERLAP_SPLIT = 3
 
     def run(self, stream=None, mask=None, describe=None, stereo=None, overlap=None):
         """The exact path.  With `overlap` (default: batches of at least
         OVERLAP_MIN_PIXELS level-0 pixels; never with a gate or a response
         dump) level-0 detection, which reads only the input, runs on a second
-        stream while the pyramid is built; the two branches join before the
+        stream while the pyramid is built (and, with one pyramid launch per
+        level, detection of levels 1..OVERLAP_SPLIT once they are built,
+        beside the later levels); the two branches join before the
         aggregation (also inside a captured graph)."""
         describe = self.describe if describe is None else describe
         stereo = self.stereo if stereo is None else stereo
@@ -114,8 +120,23 @@ class Frontend:
             side = self._side()
             side.wait_stream(st)
             vsfe.fast_br_detect_levels(c, b, self.images, self.pyr, None, self.cell_keys, 0, 1, self.status, side)
-            vsfe.pyramid_build(c, b, self.images, self.pyr, self.status, st)
-            vsfe.fast_br_detect_levels(c, b, self.images, self.pyr, None, self.cell_keys, 1, L, self.status, st)
+            if L > self.OVERLAP_SPLIT + 1 and vsfe.batch_pyramid_get(b)[0] == vsfe.PYR_LEVELS:
+                # levels 1..3 are detected on the second stream too, while
+                # the pyramid's later levels are built (≈ 25 µs per 1080p
+                # step: the launches' ramps and tails overlap)
+                k = self.OVERLAP_SPLIT
+                vsfe.pyramid_build_levels(c, b, self.images, self.pyr, 1, k + 1, self.status, st)
+                ev = torch.cuda.Event()
+                ev.record(st)
+                side.wait_event(ev)
+                vsfe.fast_br_detect_levels(c, b, self.images, self.pyr, None, self.cell_keys, 1, k + 1, self.status,
+                                           side)
+                vsfe.pyramid_build_levels(c, b, self.images, self.pyr, k + 1, L, self.status, st)
+                vsfe.fast_br_detect_levels(c, b, self.images, self.pyr, None, self.cell_keys, k + 1, L, self.status,
+                                           st)
+            else:
+                vsfe.pyramid_build(c, b, self.images, self.pyr, self.status, st)
+                vsfe.fast_br_detect_levels(c, b, self.images, self.pyr, None, self.cell_keys, 1, L, self.status, st)
             st.wait_stream(side)
         else:
             vsfe.pyramid_build(c, b, self.images, self.pyr, self.status, stream)

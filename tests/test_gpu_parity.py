@@ -28,12 +28,16 @@ def fe_mod():
 
 
 def run_and_compare(fe_mod, imgs, params, pattern, full_stages=True, tile=None, mask=None, describe=True,
-                    overlap=None):
+                    overlap=None, schedule=None):
     sizes = [(im.shape[1], im.shape[0]) for im in imgs]
-    say("case: sizes=%s params=%s tile=%s mask=%s" % (sizes[:4], params, tile, mask is not None))
+    say("case: sizes=%s params=%s tile=%s mask=%s schedule=%s" % (sizes[:4], params, tile, mask is not None,
+                                                                  schedule))
     fe = fe_mod.Frontend(params, sizes, pattern, tile=tile, with_crf=full_stages,
                          with_mask=mask is not None)
     try:
+        if schedule is not None:
+            from paper_2410_04090_amd import vsfe
+            vsfe.batch_set_pyramid(fe.batch, schedule)
         fe.upload(imgs)
         mt = None
         if mask is not None:
@@ -103,12 +107,14 @@ def test_maximum_side(fe_mod, pattern, W, H):
 
 
 @pytest.mark.parametrize("W,H", [(97, 61), (640, 17), (1241, 376)])
-def test_overlapped_path_sizes(fe_mod, pattern, W, H):
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_overlapped_path_sizes(fe_mod, pattern, W, H, schedule):
     """The overlapped run (level-0 detection on a second stream beside the
-    pyramid build, the default for large batches) against the oracle, down
-    to levels with no cell."""
+    pyramid build, the default for large batches; with one pyramid launch
+    per level also levels 1..3 there, beside the later levels) against the
+    oracle, down to levels with no cell, under both pyramid schedules."""
     l, r = scenes.stereo_pair(90 + W, W, H, 40, 12)
-    run_and_compare(fe_mod, [l, r], Params(), pattern, full_stages=False, overlap=True)
+    run_and_compare(fe_mod, [l, r], Params(), pattern, full_stages=False, overlap=True, schedule=schedule)
 
 
 def test_flat_images_no_keypoints(fe_mod, pattern):
