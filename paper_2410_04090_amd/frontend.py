@@ -19,7 +19,9 @@ def _round_up(v, a):
 
 class Frontend:
     def __init__(self, params, sizes, pattern, device="cuda", tile=None, with_crf=False,
-                 with_mask=False):
+                 with_mask=False, layout=None):
+        """layout: None (64-byte pitches, 256-byte image offsets: every row
+        16-byte aligned) or (pitches, offsets) of the input buffer."""
         self.params = vsfe.make_params(params)
         self.sizes = [(int(w), int(h)) for (w, h) in sizes]
         self.n = len(self.sizes)
@@ -27,11 +29,15 @@ class Frontend:
         self.ctx = vsfe.ctx_create(self.params, pattern)
         if tile is not None:
             vsfe.ctx_set_tile(self.ctx, *tile)
-        self.pitches = [_round_up(w, 64) for (w, _) in self.sizes]
-        self.offsets, at = [], 0
-        for (w, h), pt in zip(self.sizes, self.pitches):
-            self.offsets.append(at)
-            at = _round_up(at + pt * h, 256)
+        if layout is None:
+            self.pitches = [_round_up(w, 64) for (w, _) in self.sizes]
+            self.offsets, at = [], 0
+            for (w, h), pt in zip(self.sizes, self.pitches):
+                self.offsets.append(at)
+                at = _round_up(at + pt * h, 256)
+        else:
+            self.pitches = [int(v) for v in layout[0]]
+            self.offsets = [int(v) for v in layout[1]]
         self.batch = vsfe.batch_create(self.ctx, [w for w, _ in self.sizes], [h for _, h in self.sizes],
                                        self.pitches, self.offsets)
         info = vsfe.batch_info(self.batch)

@@ -28,12 +28,12 @@ def fe_mod():
 
 
 def run_and_compare(fe_mod, imgs, params, pattern, full_stages=True, tile=None, mask=None, describe=True,
-                    overlap=None, schedule=None):
+                    overlap=None, schedule=None, layout=None):
     sizes = [(im.shape[1], im.shape[0]) for im in imgs]
-    say("case: sizes=%s params=%s tile=%s mask=%s schedule=%s" % (sizes[:4], params, tile, mask is not None,
-                                                                  schedule))
+    say("case: sizes=%s params=%s tile=%s mask=%s schedule=%s layout=%s" % (sizes[:4], params, tile,
+                                                                            mask is not None, schedule, layout))
     fe = fe_mod.Frontend(params, sizes, pattern, tile=tile, with_crf=full_stages,
-                         with_mask=mask is not None)
+                         with_mask=mask is not None, layout=layout)
     try:
         if schedule is not None:
             from paper_2410_04090_amd import vsfe
@@ -352,3 +352,27 @@ def test_pyramid_schedule_errors(fe_mod, pattern):
         assert vsfe.batch_pyramid_get(fe.batch) == before
     finally:
         fe.close()
+
+
+@pytest.mark.parametrize("align", [1, 4])
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_unaligned_input_layout(fe_mod, pattern, align, schedule):
+    """Input rows that are not 16-byte aligned (every level-0 read takes its
+    byte-load path): odd pitches and offsets (align 1), and 4-byte aligned
+    ones that are not 16-byte aligned (align 4: ORB and refinement read
+    dwords, pyramid and detector bytes), under both pyramid schedules."""
+    sizes = [(401, 257), (401, 257), (130, 77), (130, 77)]
+    imgs = []
+    for k in range(0, len(sizes), 2):
+        w, h = sizes[k]
+        imgs += list(scenes.stereo_pair(600 + k, w, h, 60, 20))
+    pitches, offsets, at = [], [], align
+    for (w, h) in sizes:
+        pt = w + (3 if align == 1 else 4 + (-w) % 4)
+        pitches.append(pt)
+        offsets.append(at)
+        at += pt * h + (5 if align == 1 else 4)
+        if align == 4 and at % 16 == 0:
+            at += 4
+    assert any(o % 16 for o in offsets) and any(pt % 16 for pt in pitches)
+    run_and_compare(fe_mod, imgs, Params(), pattern, layout=(pitches, offsets), schedule=schedule)

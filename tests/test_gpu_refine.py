@@ -25,10 +25,10 @@ def torch_mod():
     return torch
 
 
-def run_case(torch, pairs, params, settings):
+def run_case(torch, pairs, params, settings, layout=None):
     from paper_2410_04090_amd.frontend import Frontend
     imgs = [im for pr in pairs for im in pr]
-    fe = Frontend(params, [(im.shape[1], im.shape[0]) for im in imgs], pat.brief_pattern())
+    fe = Frontend(params, [(im.shape[1], im.shape[0]) for im in imgs], pat.brief_pattern(), layout=layout)
     try:
         fe.upload(imgs)
         fe.run()
@@ -72,4 +72,19 @@ def test_refine_smallest_border_largest_window(torch_mod):
     # radius: windows reach the level edges (7 + 7 < 15)
     pair = scenes.stereo_pair(8005, 400, 256, 120, 40)
     n = run_case(torch_mod, [pair], Params(border=15), [(7, 7), (7, 1)])
+    assert n > 0
+
+
+@pytest.mark.parametrize("align", [1, 4])
+def test_refine_unaligned_input_layout(torch_mod, align):
+    """Level-0 rows not 4-byte aligned (align 1: byte reads) or 4-byte but
+    not 16-byte aligned (align 4: dword reads)."""
+    pairs = [scenes.stereo_pair(8006, 401, 257, 100, 30)]
+    pitches, offsets, at = [], [], align
+    for _ in range(2):
+        pt = 401 + (3 if align == 1 else 7)
+        pitches.append(pt)
+        offsets.append(at)
+        at += pt * 257 + (5 if align == 1 else 8)
+    n = run_case(torch_mod, pairs, Params(), [(5, 5), (7, 7)], layout=(pitches, offsets))
     assert n > 0
