@@ -6,7 +6,13 @@
 // evaluated here as a horizontal then a vertical integer lerp (the same
 // exact sum, factored: h = 256 a + fx (b - a), v = 256 h0 + fy (h1 - h0)).
 //
-// One launch per level covers that level of every image.  A block writes a
+// Two schedules build the same bytes.  Per level (large batches, where
+// the launches stream HBM): one launch per level covers that level of every
+// image.  Single launch (small and mixed batches, where seven dependent
+// launches dominate): pyramid_tower_kernel below builds every level of a
+// tile in LDS from one level-0 window.
+//
+// Per-level schedule: a block writes a
 // 256 x 32 output tile: it stages the source window (chosen on the host, at
 // most 336 x 44 bytes) in LDS with 16-byte loads and reads per-column and
 // per-row source indices and weights from host-built tables (no division on
