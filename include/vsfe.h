@@ -261,7 +261,7 @@ int32_t vsfe_batch_autotune(const vsfe_ctx *ctx, vsfe_batch *b, const uint8_t *i
  * shader-clock cycles and 100 MHz wall-clock ticks that block 0 spent in
  * its loop, whose ratio is the clock the device ran at.  Time the call with
  * events on `stream`.  Errors: EINVAL (kind, blocks or iters outside
- * 1..2^20, null buffers), EHIP. */
+ * 1..2^20, blocks x iters above 2^26, null buffers), EHIP. */
 #define VSFE_PROBE_VALU 1
 #define VSFE_PROBE_LDS  2
 int32_t vsfe_probe(int32_t kind, int32_t blocks, int32_t iters, void *sink, uint64_t *clocks, void *stream);

@@ -92,6 +92,9 @@ extern "C" int32_t vsfe_probe(int32_t kind, int32_t blocks, int32_t iters, void 
     if (kind != VSFE_PROBE_VALU && kind != VSFE_PROBE_LDS) return fail(VSFE_EINVAL, "unknown probe");
     if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
         return fail(VSFE_EINVAL, "blocks and iters must be in 1..2^20");
+    // bounded work: at most 2^26 block-trips (about 0.1 s of either probe)
+    if ((int64_t)blocks * iters > ((int64_t)1 << 26))
+        return fail(VSFE_EINVAL, "blocks x iters must be at most 2^26");
     if (!sink || !clocks) return fail(VSFE_EINVAL, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     if (kind == VSFE_PROBE_VALU)

@@ -129,6 +129,7 @@ def test_probe_argument_checks():
                                               (vsfe.PROBE_VALU, 0, 1, dummy, dummy),
                                               (vsfe.PROBE_LDS, 1, 0, dummy, dummy),
                                               (vsfe.PROBE_VALU, 1 << 21, 1, dummy, dummy),
+                                              (vsfe.PROBE_LDS, 1 << 14, 1 << 13, dummy, dummy),
                                               (vsfe.PROBE_VALU, 1, 1, None, dummy),
                                               (vsfe.PROBE_LDS, 1, 1, dummy, None)):
         assert L.vsfe_probe(kind, blocks, iters, sink, clocks, None) == vsfe.EINVAL
