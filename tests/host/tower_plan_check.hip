@@ -146,6 +146,8 @@ int main() {
                       {8192, 160}, {160, 8192}, {1, 1}, {2, 3}, {17, 9}, {400, 256}, {333, 201}, {1024, 768}};
     for (auto &s : sizes) run(s[0], s[1], TWR_TW, TWR_TH, 8, 1);
     for (auto &s : sizes) run(s[0], s[1], TWR_TW, TWR_TH, 12, 2);
+    for (auto &s : sizes) run(s[0], s[1], TWR_TW, TWR_TH, 2, 6);
+    for (auto &s : sizes) run(s[0], s[1], 64, 16, 3, 7);
     int tiles[][2] = {{16, 4}, {64, 16}, {128, 32}, {240, 64}, {200, 40}, {48, 8}, {240, 4}, {16, 64}};
     for (auto &t : tiles) {
         run(1241, 376, t[0], t[1], 8, 3);

@@ -127,6 +127,7 @@ def test_flat_images_no_keypoints(fe_mod, pattern):
     dict(nms_mode=1), dict(nms_radius=0), dict(nms_radius=2), dict(nms_radius=3),
     dict(p_max=16, eps_lo=-1), dict(pfa=0, n_max=5000), dict(blur=0), dict(eps_hi=35, eps_lo=12),
     dict(cell0=16, n_levels=6), dict(p_min=12, p_max=14), dict(row_band=0, d_max=40, match_th=90),
+    dict(n_levels=1), dict(n_levels=2), dict(n_levels=3),
 ])
 def test_parameter_variants(fe_mod, pattern, variant):
     l, r = scenes.stereo_pair(77, 420, 260, 90, 40)
@@ -376,3 +377,39 @@ def test_unaligned_input_layout(fe_mod, pattern, align, schedule):
             at += 4
     assert any(o % 16 for o in offsets) and any(pt % 16 for pt in pitches)
     run_and_compare(fe_mod, imgs, Params(), pattern, layout=(pitches, offsets), schedule=schedule)
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_pyramid_level_ranges(fe_mod, pattern, schedule):
+    """pyramid_build_levels (one launch per level whatever the batch's
+    schedule) over split ranges, the later range on a second stream after
+    the first, builds the oracle's levels; ranges out of bounds are
+    refused."""
+    import torch
+    from paper_2410_04090_amd import vsfe
+    sizes = [(640, 360), (640, 360), (333, 201), (333, 201)]
+    imgs = [scenes.random_image(950 + k, w, h) for k, (w, h) in enumerate(sizes)]
+    p = Params()
+    fe = fe_mod.Frontend(p, sizes, pattern)
+    try:
+        vsfe.batch_set_pyramid(fe.batch, schedule)
+        fe.upload(imgs)
+        L = p.n_levels
+        for cut in (2, 4, 7):
+            say("case: schedule=%d ranges [1, %d) [%d, %d)" % (schedule, cut, cut, L))
+            fe.pyr.fill_(0)
+            main = torch.cuda.current_stream()
+            vsfe.pyramid_build_levels(fe.ctx, fe.batch, fe.images, fe.pyr, 1, cut, fe.status, main)
+            side = torch.cuda.Stream()
+            side.wait_stream(main)
+            vsfe.pyramid_build_levels(fe.ctx, fe.batch, fe.images, fe.pyr, cut, L, fe.status, side)
+            main.wait_stream(side)
+            torch.cuda.synchronize()
+            for i, img in enumerate(imgs):
+                compare_pyramid(fe, i, img, p)
+        for lo, hi in ((0, 2), (2, 2), (3, 1), (1, L + 1)):
+            with pytest.raises(vsfe.VsfeError):
+                vsfe.pyramid_build_levels(fe.ctx, fe.batch, fe.images, fe.pyr, lo, hi, fe.status)
+        assert int(fe.status.item()) == 0
+    finally:
+        fe.close()

@@ -1,6 +1,6 @@
 """The single-launch pyramid's host planner and the kernel's indexing,
 replayed on the CPU (tests/host/tower_plan_check.hip) for 16 image sizes
-with 8 and 12 levels and 8 tile shapes, against the oracle pyramid: every
+with 2, 3, 8 and 12 levels and 8 tile shapes, against the oracle pyramid: every
 level bit-exact, every pixel written once, no LDS access outside its
 buffer, no weighted read of a byte the level above did not write."""
 import os
