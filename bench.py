@@ -322,12 +322,60 @@ def learned_path(args, fe, sizes, stream, exact_value):
     ones = torch.ones_like(fe.cell_mask)
     calls["fast_br_detect_all_cells_kept"] = lambda: vsfe.fast_br_detect(c, b, fe.images, fe.pyr, ones, fe.cell_keys,
                                                                          None, fe.status, stream)
+    ideal, ideal_res = ideal_gate(args, fe, sizes, stream, exact, exact_value)
+    calls["fast_br_detect_ideal_mask"] = lambda: vsfe.fast_br_detect(c, b, fe.images, fe.pyr, ideal, fe.cell_keys,
+                                                                     None, fe.status, stream)
     call_us = {k: round(time_call(f, args.kernel_reps, stream), 2) for k, f in calls.items()}
     value = (len(sizes) // 2) * 1000.0 / ms
     return {"value": round(value, 1), "unit": "stereo pairs/s", "ms_per_step": round(ms, 4),
             "speedup_vs_exact": round(value / exact_value, 4), "recall": round(hit / max(ref_n, 1), 5),
             "precision": round(hit / max(sum(len(g) for g in got), 1), 5), "kept_cell_frac": round(kept, 4),
-            "thresh": tau, "weights": os.path.relpath(path, ROOT), "calls_us": call_us}
+            "thresh": tau, "weights": os.path.relpath(path, ROOT), "calls_us": call_us,
+            "ideal_gate": ideal_res}
+
+
+def ideal_gate(args, fe, sizes, stream, exact, exact_value):
+    """The gate's ceiling on this batch: the path gated by exactly the
+    native-scale cells that hold a final keypoint of the exact path (what a
+    proposer with perfect recall would keep at the smallest kept fraction),
+    with no proposer at all.  Returns the mask and the timed result."""
+    import torch
+    from paper_2410_04090_amd import labels
+    torch.cuda.synchronize()
+    fe.run()
+    counts = fe.kp_count.cpu().numpy()
+    n_max = fe.params.n_max
+    x0 = fe.kps["x0"].cpu().numpy().view(np.uint16)
+    y0 = fe.kps["y0"].cpu().numpy().view(np.uint16)
+    parts = []
+    for i, (w, h) in enumerate(sizes):
+        s = slice(i * n_max, i * n_max + int(counts[i]))
+        parts.append(labels.positive_cells(x0[s], y0[s], w, h).reshape(-1))
+    mask = np.concatenate(parts).astype(np.uint8)
+    if mask.size != fe.cell_mask.numel():
+        raise RuntimeError("native-scale cell count %d differs from the batch's %d" % (mask.size, fe.cell_mask.numel()))
+    ideal = torch.from_numpy(mask).to(fe.cell_mask.device)
+    fe.run(mask=ideal)
+    got = keypoint_sets(fe)
+    ref_n = sum(len(r) for r in exact)
+    hit = sum(len(r & g) for r, g in zip(exact, got))
+    g3 = fe.capture(fe.run, mask=ideal)
+    for _ in range(args.warmup):
+        g3.replay()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        g3.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    value = (len(sizes) // 2) * 1000.0 / ms
+    return ideal, {"what": "gated by the cells holding a final keypoint of the exact path, no proposer",
+                   "value": round(value, 1), "ms_per_step": round(ms, 4),
+                   "speedup_vs_exact": round(value / exact_value, 4), "recall": round(hit / max(ref_n, 1), 5),
+                   "kept_cell_frac": round(float(mask.mean()), 4)}
 
 
 def middle_end(args, fe, stream):
