@@ -197,6 +197,8 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
 constexpr int SEL_THREADS = 1024;
 constexpr int SEL_WAVES = SEL_THREADS / 64;
 constexpr int SEL_LDS_CELLS = 24576;      // an image's ranks are cached in LDS up to this many cells
+constexpr int SEL_CHUNK = 8;              // cells per thread whose rank and key are read together
+constexpr int SEL_IDX_SLOTS = 8192;       // keypoints per image written out slot by slot (beyond: cell by cell)
 
 // Exclusive prefix sums of two per-thread counts over the block; *tot_a /
 // *tot_b get the totals.  Two barriers: every thread must call it.
@@ -262,7 +264,10 @@ __device__ __forceinline__ void find_bucket(const int *hist, int base, int need,
 
 // One block per image.  The image's ranks are read once (into LDS when
 // they fit); the compaction gives each thread a contiguous run of cells, so
-// one block scan of the per-thread counts places every survivor.
+// one block scan of the per-thread counts places every survivor.  Up to
+// SEL_IDX_SLOTS survivors, the threads first record the cell of every slot
+// in LDS and then write the keypoints one slot per thread (coalesced);
+// beyond that, each thread writes its own cells' keypoints.
 __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
     const ImageDev *__restrict__ imgs, const uint32_t *__restrict__ cell_keys, const uint32_t *__restrict__ rank,
     vsfe_kp_soa kps, int32_t *__restrict__ kp_count, int n_max, int32_t *status, PfaLevelTab tab) {
@@ -270,12 +275,24 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
     __shared__ int hist[1024];
     __shared__ int wave_a[SEL_WAVES], wave_b[SEL_WAVES];
     __shared__ int s_sel[3];   // threshold T, count of ranks > T, bucket
+    // the image's level records as the compaction reads them (first cell
+    // relative to the image, cells per row, cell size, scale, offset divisor)
+    __shared__ int4 s_lv[VSFE_MAX_LEVELS];
+    __shared__ uint32_t s_mag[VSFE_MAX_LEVELS];
+    __shared__ int s_idx[SEL_IDX_SLOTS];      // slot -> cell of the image
     const ImageDev &im = imgs[blockIdx.x];
     const int64_t base = im.cell_base;
     const int n = (int)im.n_cells;
+    const int n_levels = im.n_levels, W = im.w, H = im.h;
+    const int64_t kp0 = im.kp_offset;
     const int tid = threadIdx.x;
     const bool cached = n <= SEL_LDS_CELLS;
     auto rk = [&](int i) { return cached ? s_rank[i] : rank[base + i]; };
+    if (tid < n_levels) {
+        const LevelDev &L = im.lv[tid];
+        s_lv[tid] = make_int4((int)(L.cell_offset - base), L.ncx, L.cell, L.scale_q16);
+        s_mag[tid] = tab.mag[tid];
+    }
 
     // pass 1: histogram of the high 10 bits of the nonzero ranks (ranks <
     // 2^20); its total is the number of survivors.  Four loads per thread
@@ -338,49 +355,100 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
     }
     int gt_before, eq_before, gt_all, eq_all;
     block_scan2(n_gt, n_eq, wave_a, wave_b, &gt_before, &eq_before, &gt_all, &eq_all);
-    int l = 0;
-    while (l + 1 < im.n_levels && im.lv[l + 1].cell_offset - base <= i0) l++;
-    for (int i = i0; i < i1; i++) {
-        const uint32_t v = rk(i);
-        const bool gt = v != 0 && v > T;
-        const bool eq = v != 0 && T != 0 && v == T;
-        const bool keep = gt || (eq && eq_before < quota);
-        const int slot = gt_before + min(eq_before, quota);
-        gt_before += gt ? 1 : 0;
-        eq_before += eq ? 1 : 0;
-        if (!keep) continue;
-        while (l + 1 < im.n_levels && im.lv[l + 1].cell_offset - base <= i) l++;
-        const LevelDev &lv = im.lv[l];
-        const int li = (int)(i - (lv.cell_offset - base));
-        const uint32_t key = cell_keys[base + i];
+    const int kept = gt_all + min(eq_all, quota);
+    // keypoint stores through global pointers (they cannot touch the LDS
+    // tables read between them)
+    typedef __attribute__((address_space(1))) uint32_t g32;
+    typedef __attribute__((address_space(1))) uint16_t g16;
+    typedef __attribute__((address_space(1))) uint8_t g8;
+    g16 *const o_x = (g16 *)kps.x, *const o_y = (g16 *)kps.y, *const o_score = (g16 *)kps.score;
+    g16 *const o_x0 = (g16 *)kps.x0, *const o_y0 = (g16 *)kps.y0;
+    g32 *const o_kr = (g32 *)kps.kr;
+    g8 *const o_level = (g8 *)kps.level, *const o_flags = (g8 *)kps.flags, *const o_kl = (g8 *)kps.kl;
+    g8 *const o_bin = (g8 *)kps.bin;
+    // the keypoint of cell i (level l, rank v, key) into slot `slot`
+    auto emit = [&](int i, int l, uint32_t v, uint32_t key, int slot) {
+        const int4 lv = s_lv[l];                       // (first cell, ncx, cell, scale)
+        const int li = i - lv.x;
         // li / ncx by a float reciprocal and one correction step (li <
         // 2^24, so the estimate is off by at most one); off / c by the
         // level's multiplier (off < 1024)
-        const int c = lv.cell;
-        int cy = (int)((float)li * __builtin_amdgcn_rcpf((float)lv.ncx));
-        int cx = li - cy * lv.ncx;
-        if (cx < 0) { cy--; cx += lv.ncx; }
-        if (cx >= lv.ncx) { cy++; cx -= lv.ncx; }
+        const int c = lv.z;
+        int cy = (int)((float)li * __builtin_amdgcn_rcpf((float)lv.y));
+        int cx = li - cy * lv.y;
+        if (cx < 0) { cy--; cx += lv.y; }
+        if (cx >= lv.y) { cy++; cx -= lv.y; }
         const int off = 1023 - (int)(key & 1023u);
-        const int oy = (int)(__umul24((uint32_t)off, tab.mag[l]) >> 20);
+        const int oy = (int)(__umul24((uint32_t)off, s_mag[l]) >> 20);
         const int x = cx * c + (off - oy * c), y = cy * c + oy;
-        if (slot < n_max) {
-            const int64_t o = im.kp_offset + slot;
-            kps.x[o] = (uint16_t)x;
-            kps.y[o] = (uint16_t)y;
-            kps.level[o] = (uint8_t)l;
-            kps.flags[o] = (key & VSFE_KEY_FALLBACK) ? (uint8_t)VSFE_KP_FALLBACK : (uint8_t)0;
-            kps.score[o] = (uint16_t)((key >> 10) & 0xFFFu);
-            kps.x0[o] = (uint16_t)project_q16(x, lv.scale_q16, im.w);
-            kps.y0[o] = (uint16_t)project_q16(y, lv.scale_q16, im.h);
-            kps.kl[o] = (uint8_t)(v >> 16);
-            kps.kr[o] = v & 0xFFFFu;
-            kps.bin[o] = 0;
-        } else if (status) {
-            atomicOr(status, VSFE_DEV_OVERFLOW);
+        const int64_t o = kp0 + slot;
+        o_x[o] = (uint16_t)x;
+        o_y[o] = (uint16_t)y;
+        o_level[o] = (uint8_t)l;
+        o_flags[o] = (key & VSFE_KEY_FALLBACK) ? (uint8_t)VSFE_KP_FALLBACK : (uint8_t)0;
+        o_score[o] = (uint16_t)((key >> 10) & 0xFFFu);
+        o_x0[o] = (uint16_t)project_q16(x, lv.w, W);
+        o_y0[o] = (uint16_t)project_q16(y, lv.w, H);
+        o_kl[o] = (uint8_t)(v >> 16);
+        o_kr[o] = v & 0xFFFFu;
+        o_bin[o] = 0;
+    };
+    if (kept <= SEL_IDX_SLOTS && kept <= n_max) {                    // uniform
+        // the slot -> cell map in LDS, then one thread per slot, so that
+        // consecutive lanes write consecutive slots (full-width stores
+        // instead of a narrow scattered store per field and kept cell)
+        for (int c0 = i0; c0 < i1; c0 += SEL_CHUNK) {
+            uint32_t vv[SEL_CHUNK];
+#pragma unroll
+            for (int u = 0; u < SEL_CHUNK; u++) vv[u] = c0 + u < i1 ? rk(c0 + u) : 0u;
+#pragma unroll
+            for (int u = 0; u < SEL_CHUNK; u++) {
+                const uint32_t v = vv[u];                // (cells past i1 have v = 0)
+                const bool gt = v != 0 && v > T;
+                const bool eq = v != 0 && T != 0 && v == T;
+                const bool keep = gt || (eq && eq_before < quota);
+                if (keep) s_idx[gt_before + min(eq_before, quota)] = c0 + u;   // < kept
+                gt_before += gt ? 1 : 0;
+                eq_before += eq ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        for (int slot = tid; slot < kept; slot += SEL_THREADS) {
+            const int i = s_idx[slot];
+            int l = 0;
+            while (l + 1 < n_levels && s_lv[l + 1].x <= i) l++;
+            emit(i, l, rk(i), cell_keys[base + i], slot);
+        }
+    } else {
+        // each thread its own cells in chunks of SEL_CHUNK (ranks and keys of
+        // a chunk read together)
+        int l = 0;
+        while (l + 1 < n_levels && s_lv[l + 1].x <= i0) l++;
+        for (int c0 = i0; c0 < i1; c0 += SEL_CHUNK) {
+            uint32_t vv[SEL_CHUNK], kk[SEL_CHUNK];
+#pragma unroll
+            for (int u = 0; u < SEL_CHUNK; u++) {
+                const int i = c0 + u;
+                vv[u] = i < i1 ? rk(i) : 0u;
+                kk[u] = i < i1 ? cell_keys[base + i] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < SEL_CHUNK; u++) {
+                const int i = c0 + u;
+                const uint32_t v = vv[u];
+                const bool gt = v != 0 && v > T;
+                const bool eq = v != 0 && T != 0 && v == T;
+                const bool keep = gt || (eq && eq_before < quota);
+                const int slot = gt_before + min(eq_before, quota);
+                gt_before += gt ? 1 : 0;
+                eq_before += eq ? 1 : 0;
+                if (!keep) continue;                       // (cells past i1 have v = 0)
+                while (l + 1 < n_levels && s_lv[l + 1].x <= i) l++;
+                if (slot < n_max) emit(i, l, v, kk[u], slot);
+                else if (status) atomicOr(status, VSFE_DEV_OVERFLOW);
+            }
         }
     }
-    const int kept = gt_all + min(eq_all, quota);
     if (tid == 0) kp_count[blockIdx.x] = kept < n_max ? kept : n_max;
 }
 

@@ -91,6 +91,15 @@ def test_random_dense_pairs_with_cap(fe_mod, pattern, seed):
     assert len(refs[0]["x"]) == 150
 
 
+def test_more_keypoints_than_the_slot_map(fe_mod, pattern):
+    """Over 8192 keypoints per image (small cells, no PFA, no binding cap):
+    the aggregation writes them out cell by cell instead of slot by slot."""
+    l, r = scenes.stereo_pair(5, 1280, 960, 600, 64)
+    p = Params(cell0=16, pfa=0, n_max=65535)
+    _, refs, _ = run_and_compare(fe_mod, [l, r], p, pattern, full_stages=False)
+    assert min(len(ref["x"]) for ref in refs) > 8192
+
+
 @pytest.mark.parametrize("W,H", [(97, 61), (130, 77), (33, 33), (640, 17)])
 def test_ragged_and_tiny_sizes(fe_mod, pattern, W, H):
     """Odd sizes, partial cells, and levels narrower than twice the border."""
