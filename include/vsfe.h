@@ -355,8 +355,11 @@ int32_t orb_describe(const vsfe_ctx *ctx, const vsfe_batch *b, const uint8_t *im
  * d = x0_l - x0_r in [0, d_max] of least Hamming distance (ties: smaller
  * |dy|, smaller d, smaller index); accepted if distance <= match_th.
  * Outputs (match_capacity, slot pair * n_max + i): match_idx (right index
- * or -1), match_dist (0xFFFF if none), match_disp (-1 if none).  EINVAL if
- * the batch has an odd image count or a pair of unequal sizes. */
+ * or -1), match_dist (0xFFFF if none), match_disp (-1 if none).  The
+ * keypoints must be in canonical order, as pyca_cull_aggregate writes them
+ * (in any other order the matches are unspecified, and every read stays
+ * inside the image's slots).  EINVAL if the batch has an odd image count or
+ * a pair of unequal sizes. */
 int32_t stereo_match(const vsfe_ctx *ctx, const vsfe_batch *b, const vsfe_kp_soa *kps,
                      const int32_t *kp_count, const uint32_t *desc, int32_t *match_idx,
                      uint16_t *match_dist, int16_t *match_disp, int32_t *status, void *stream);

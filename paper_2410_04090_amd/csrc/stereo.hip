@@ -5,10 +5,12 @@
 // order (level, cell row, cell column), so the candidates of a left
 // keypoint at level l and row y -- same level, |dy| <= row_band -- lie in
 // the contiguous run of cell rows floor((y - band) / c_l) ..
-// floor((y + band) / c_l).  A first pass writes, for every cell row of every
-// right image, the index of its first keypoint (one thread per keypoint
-// fills the rows from the previous keypoint's row to its own), so that run
-// is two table reads.  Each candidate
+// floor((y + band) / c_l).  On batches of at least 16384 keypoint slots a
+// first pass writes, for every cell row of every right image, the index of
+// its first keypoint (one thread per keypoint fills the rows from the
+// previous keypoint's row to its own), so that run is two table reads;
+// smaller batches search for the run's start instead (one launch less,
+// which is what a single pair's latency is made of).  Each candidate
 // with native-scale disparity d = x0_l - x0_r in [0, d_max] costs eight
 // popcounts; the least distance wins, ties to smaller |dy|, smaller d,
 // smaller index (ascending scan with strict comparisons).
@@ -51,8 +53,12 @@ __global__ __launch_bounds__(256) void row_table_kernel(const ImageDev *__restri
 // few keypoints leave the GPU waiting on each candidate walk): lane k scans
 // candidates start + k, + G, ... and the group keeps the least (distance,
 // |dy|, disparity, index) key, which is the ascending scan's choice with
-// strict comparisons
-template <int ST_GROUP>
+// strict comparisons.  SEARCH (16 lanes, small batches): no row-start
+// table; the group finds the first candidate by a 16-way search over the
+// right keypoints, and each lane's walk stops at its first keypoint past
+// the last candidate row (the same candidates for keypoints in canonical
+// order; any order stays inside the image's slots).
+template <int ST_GROUP, bool SEARCH>
 __global__ __launch_bounds__(256) void stereo_kernel(const ImageDev *__restrict__ imgs, vsfe_kp_soa kps,
                                                      const int32_t *__restrict__ kp_count,
                                                      const uint32_t *__restrict__ desc, int32_t *__restrict__ midx,
@@ -76,15 +82,48 @@ __global__ __launch_bounds__(256) void stereo_kernel(const ImageDev *__restrict_
     const LevelDev &rl = imgs[ri].lv[level];
     const int c = a.cell[level];
     const int cy_lo = max(y - a.band, 0) / c, cy_hi = min((y + a.band) / c, rl.ncy - 1);
-    // (clamped to [0, nr]: with keypoints out of canonical order some
-    // entries are not written, and no read may leave the image's slots)
-    const int start = min(max(tab[rl.row_tab + cy_lo], 0), nr);
-    const int end = min(max(tab[rl.row_tab + cy_hi + 1], start), nr);
+    int start, end;
+    if constexpr (SEARCH) {
+        static_assert(ST_GROUP == 16, "the search takes a group of 16 lanes");
+        // first right keypoint at (level, row cy_lo) or after: each step the
+        // group probes 16 evenly spaced keypoints of [lo, hi) and keeps the
+        // gap after the last one that is still before the target
+        int lo = 0, hi = nr;
+        const int gshift = (int)(threadIdx.x & 63) & ~(ST_GROUP - 1);
+        while (lo < hi) {                                  // (uniform in the group)
+            const int step = (hi - lo + ST_GROUP - 1) / ST_GROUP;
+            const int p = lo + k * step;
+            bool before = false;
+            if (p < hi) {
+                const int64_t rs = rbase + p;
+                const int lp = kps.level[rs];
+                before = lp < level || (lp == level && (int)kps.y[rs] / c < cy_lo);
+            }
+            const int cnt = __popcll((__ballot(before) >> gshift) & 0xFFFFull);
+            if (cnt == 0) {
+                hi = lo;
+            } else {
+                const int pt = lo + (cnt - 1) * step;
+                hi = min(pt + step, hi);
+                lo = pt + 1;
+            }
+        }
+        start = lo;
+        end = nr;
+    } else {
+        // (clamped to [0, nr]: with keypoints out of canonical order some
+        // entries are not written, and no read may leave the image's slots)
+        start = min(max(tab[rl.row_tab + cy_lo], 0), nr);
+        end = min(max(tab[rl.row_tab + cy_hi + 1], start), nr);
+    }
 
     // key = distance << 40 | |dy| << 32 | disparity << 16 | index (no candidate: all ones)
     uint64_t key = ~(uint64_t)0;
     for (int j = start + k; j < end; j += ST_GROUP) {
         const int64_t rs = rbase + j;
+        if constexpr (SEARCH) {
+            if (kps.level[rs] != level || (int)kps.y[rs] / c > cy_hi) break;   // past the last candidate row
+        }
         int dy = (int)kps.y[rs] - y;
         dy = dy < 0 ? -dy : dy;
         if (dy > a.band) continue;
@@ -139,21 +178,24 @@ extern "C" int32_t stereo_match(const vsfe_ctx *ctx, const vsfe_batch *b, const 
     const int64_t n = (int64_t)a.n_pairs * a.n_max;
     if (n <= 0) return VSFE_OK;
     if (!b->d_row_tab) return fail(VSFE_EINVAL, "batch has no row-start table");
-    const int64_t nt = (int64_t)a.n_pairs * (a.n_max + 1);
-    hipLaunchKernelGGL(row_table_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       b->d_images, *kps, kp_count, b->d_row_tab, a);
-    rc = check_launch("stereo_match (row table)");
-    if (rc) return rc;
     if (n >= ((int64_t)1 << 27)) return fail(VSFE_ECAPACITY, "too many keypoint slots");
     const hipStream_t st = (hipStream_t)stream;
-    if (n < 16384)
-        hipLaunchKernelGGL(stereo_kernel<16>, dim3((unsigned)((n * 16 + 255) / 256)), dim3(256), 0, st, b->d_images,
-                           *kps, kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
-    else if (n < 131072)
-        hipLaunchKernelGGL(stereo_kernel<4>, dim3((unsigned)((n * 4 + 255) / 256)), dim3(256), 0, st, b->d_images,
-                           *kps, kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
+    if (n < 16384) {
+        // small batches: the candidate rows are searched for, no table launch
+        hipLaunchKernelGGL((stereo_kernel<16, true>), dim3((unsigned)((n * 16 + 255) / 256)), dim3(256), 0, st,
+                           b->d_images, *kps, kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
+        return check_launch("stereo_match");
+    }
+    const int64_t nt = (int64_t)a.n_pairs * (a.n_max + 1);
+    hipLaunchKernelGGL(row_table_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, b->d_images, *kps,
+                       kp_count, b->d_row_tab, a);
+    rc = check_launch("stereo_match (row table)");
+    if (rc) return rc;
+    if (n < 131072)
+        hipLaunchKernelGGL((stereo_kernel<4, false>), dim3((unsigned)((n * 4 + 255) / 256)), dim3(256), 0, st,
+                           b->d_images, *kps, kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
     else
-        hipLaunchKernelGGL(stereo_kernel<1>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, b->d_images, *kps,
-                           kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
+        hipLaunchKernelGGL((stereo_kernel<1, false>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                           b->d_images, *kps, kp_count, desc, match_idx, match_dist, match_disp, b->d_row_tab, a);
     return check_launch("stereo_match");
 }
