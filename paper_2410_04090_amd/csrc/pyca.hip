@@ -154,12 +154,19 @@ __global__ __launch_bounds__(256) void pfa_eval_kernel(const ImageDev *__restric
                 if (window(m, L, &a0, &a1, &b0, &b1)) {
                     ca[m] = a0;
                     cb[m] = b0;
-                    const uint32_t *row0 = cell_keys + L.cell_offset + __umul24(b0, L.ncx);
+                    // 32-bit byte offsets from the level's uniform base (a
+                    // level holds fewer than 2^24 cells), so each load is
+                    // one vector offset on a scalar address
+                    typedef const __attribute__((address_space(1))) uint8_t gbyte;
+                    typedef const __attribute__((address_space(1))) uint32_t gword;
+                    gbyte *kb = (gbyte *)(cell_keys + L.cell_offset);
+                    const uint32_t o0 = 4u * (__umul24((uint32_t)b0, (uint32_t)L.ncx) + (uint32_t)a0);
+                    const uint32_t rowb = 4u * (uint32_t)L.ncx;
                     const bool ax = a0 + 1 < L.ncx, by = b0 + 1 < L.ncy;
-                    kk[m][0] = row0[a0];
-                    if (ax) kk[m][1] = row0[a0 + 1];
-                    if (by) kk[m][2] = row0[L.ncx + a0];
-                    if (ax && by) kk[m][3] = row0[L.ncx + a0 + 1];
+                    kk[m][0] = *(gword *)(kb + o0);
+                    if (ax) kk[m][1] = *(gword *)(kb + (o0 + 4u));
+                    if (by) kk[m][2] = *(gword *)(kb + (o0 + rowb));
+                    if (ax && by) kk[m][3] = *(gword *)(kb + (o0 + rowb + 4u));
                 }
             }
         }
