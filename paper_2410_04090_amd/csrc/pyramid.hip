@@ -139,7 +139,12 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
         h01 = A01 * W01 + B01 * F01;
         h23 = A23 * W23 + B23 * F23;
     };
-    uint8_t *out = dst + (int64_t)oy0 * d.pitch + ox;
+    // output rows at 32-bit byte offsets from the level's uniform first byte
+    // (a level of the pyramid buffer holds fewer than 2^27 bytes)
+    typedef __attribute__((address_space(1))) uint8_t gbyte;
+    typedef __attribute__((address_space(1))) uint32_t gword;
+    gbyte *const obase = (gbyte *)dst;
+    uint32_t ooff = __umul24((uint32_t)oy0, (uint32_t)d.pitch) + (uint32_t)ox;
     int cur = -2;
     pu2 t01, t23, u01, u23;                              // rows cur, cur + 1
 #pragma unroll
@@ -161,11 +166,11 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(const ImageDev *__re
         // (h0 (256 - fy) + h1 fy + 2^15) >> 16 is byte 2 of the sum
         const uint32_t word = vlerp4(t01, t23, u01, u23, wf);
         if (ox + 3 < d.w) {
-            *(uint32_t *)out = word;
+            *(gword *)(obase + ooff) = word;
         } else {
-            for (int j = 0; ox + j < d.w; j++) out[j] = (uint8_t)(word >> (8 * j));
+            for (int j = 0; ox + j < d.w; j++) obase[ooff + j] = (uint8_t)(word >> (8 * j));
         }
-        out += d.pitch;
+        ooff += (uint32_t)d.pitch;
     }
 }
 
