@@ -368,11 +368,13 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
     typedef __attribute__((address_space(1))) uint32_t g32;
     typedef __attribute__((address_space(1))) uint16_t g16;
     typedef __attribute__((address_space(1))) uint8_t g8;
-    g16 *const o_x = (g16 *)kps.x, *const o_y = (g16 *)kps.y, *const o_score = (g16 *)kps.score;
-    g16 *const o_x0 = (g16 *)kps.x0, *const o_y0 = (g16 *)kps.y0;
-    g32 *const o_kr = (g32 *)kps.kr;
-    g8 *const o_level = (g8 *)kps.level, *const o_flags = (g8 *)kps.flags, *const o_kl = (g8 *)kps.kl;
-    g8 *const o_bin = (g8 *)kps.bin;
+    // (each array from the image's first slot: uniform bases, 32-bit slot offsets)
+    g16 *const o_x = (g16 *)(kps.x + kp0), *const o_y = (g16 *)(kps.y + kp0);
+    g16 *const o_score = (g16 *)(kps.score + kp0);
+    g16 *const o_x0 = (g16 *)(kps.x0 + kp0), *const o_y0 = (g16 *)(kps.y0 + kp0);
+    g32 *const o_kr = (g32 *)(kps.kr + kp0);
+    g8 *const o_level = (g8 *)(kps.level + kp0), *const o_flags = (g8 *)(kps.flags + kp0);
+    g8 *const o_kl = (g8 *)(kps.kl + kp0), *const o_bin = (g8 *)(kps.bin + kp0);
     // the keypoint of cell i (level l, rank v, key) into slot `slot`
     auto emit = [&](int i, int l, uint32_t v, uint32_t key, int slot) {
         const int4 lv = s_lv[l];                       // (first cell, ncx, cell, scale)
@@ -388,17 +390,20 @@ __global__ __launch_bounds__(SEL_THREADS) void select_compact_kernel(
         const int off = 1023 - (int)(key & 1023u);
         const int oy = (int)(__umul24((uint32_t)off, s_mag[l]) >> 20);
         const int x = cx * c + (off - oy * c), y = cy * c + oy;
-        const int64_t o = kp0 + slot;
-        o_x[o] = (uint16_t)x;
-        o_y[o] = (uint16_t)y;
-        o_level[o] = (uint8_t)l;
-        o_flags[o] = (key & VSFE_KEY_FALLBACK) ? (uint8_t)VSFE_KP_FALLBACK : (uint8_t)0;
-        o_score[o] = (uint16_t)((key >> 10) & 0xFFFu);
-        o_x0[o] = (uint16_t)project_q16(x, lv.w, W);
-        o_y0[o] = (uint16_t)project_q16(y, lv.w, H);
-        o_kl[o] = (uint8_t)(v >> 16);
-        o_kr[o] = v & 0xFFFFu;
-        o_bin[o] = 0;
+        // byte offsets computed in 32 bits (slot < 2^16), so each store is one
+        // vector offset on a scalar base
+        const uint32_t o = (uint32_t)slot;
+        auto at2 = [&](g16 *a) { return (g16 *)((g8 *)a + 2u * o); };
+        *at2(o_x) = (uint16_t)x;
+        *at2(o_y) = (uint16_t)y;
+        *(o_level + o) = (uint8_t)l;
+        *(o_flags + o) = (key & VSFE_KEY_FALLBACK) ? (uint8_t)VSFE_KP_FALLBACK : (uint8_t)0;
+        *at2(o_score) = (uint16_t)((key >> 10) & 0xFFFu);
+        *at2(o_x0) = (uint16_t)project_q16(x, lv.w, W);
+        *at2(o_y0) = (uint16_t)project_q16(y, lv.w, H);
+        *(o_kl + o) = (uint8_t)(v >> 16);
+        *(g32 *)((g8 *)o_kr + 4u * o) = v & 0xFFFFu;
+        *(o_bin + o) = 0;
     };
     if (kept <= SEL_IDX_SLOTS && kept <= n_max) {                    // uniform
         // the slot -> cell map in LDS, then one thread per slot, so that
